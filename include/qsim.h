@@ -1,0 +1,271 @@
+/*
+ * qsim.h - C ABI of the MI355X (gfx950) state-vector gate engine, libqsim.so.
+ *
+ * The engine applies a sequence of quantum gates to the state of n qubits, a vector of 2^n complex
+ * amplitudes a(x_{n-1} ... x_0), following De Raedt et al., "Massive Parallel Quantum Computer
+ * Simulator": the state and its normalisation (Sec. II.A, Eqs. STAT2 and STAT1), the elementary
+ * gates (Sec. II.B-II.D) and their in-place update rules (Sec. III.A, Eqs. NUM2-NUM8).
+ *
+ * Conventions shared by every call
+ *   - Qubit q is bit q of the amplitude index; qubit 0 is the least significant bit (Sec. II.A).
+ *   - Device layout: amplitude i is stored interleaved as (re, im) at element i of a contiguous
+ *     array: 16 bytes per amplitude for QSIM_C128 (two doubles), 8 bytes for QSIM_C64 (two floats).
+ *   - 2x2 matrices cross the ABI as 8 host doubles, row-major complex (re, im) pairs:
+ *     U = {u00r, u00i, u01r, u01i, u10r, u10i, u11r, u11i}; the update is a' = U a on every pair
+ *     (a(..0_t..), a(..1_t..)) (the common form of Eqs. NUM2-NUM8). Matrices are copied before the
+ *     call returns; complex64 states round them to FP32 at launch. Unitarity is not checked.
+ *   - Control masks: bit q set = qubit q is a control; the gate acts only on indices whose control
+ *     bits are all 1 (Eqs. NUM6-NUM8). A mask must not contain the target and must be < 2^n.
+ *   - Every apply call is asynchronous on the state's HIP stream; calls that return host data
+ *     (norm, probabilities to host, marginals, download, renormalize) synchronise that stream.
+ *   - Return codes: QSIM_OK (0) or a negative QSIM_E* code; nothing is launched when an argument is
+ *     rejected. qsim_last_error() returns the calling thread's message for the last failure.
+ *   - Thread safety: one thread per state (or external locking). Different states may be used
+ *     from different threads.
+ */
+#ifndef QSIM_H
+#define QSIM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct qsim_state qsim_state; /* opaque: device buffer + stream + small reduction buffer */
+typedef struct qsim_plan qsim_plan;   /* opaque: a circuit lowered to kernel launches */
+
+typedef enum { QSIM_C64 = 0, QSIM_C128 = 1 } qsim_dtype;
+
+enum {
+    QSIM_OK = 0,
+    QSIM_EINVAL = -1,      /* bad argument (range, null pointer, size mismatch, duplicate qubit) */
+    QSIM_ENOMEM = -2,      /* device allocation failed or the state does not fit */
+    QSIM_EDEVICE = -3,     /* a HIP runtime error; text in qsim_last_error() */
+    QSIM_EUNSUPPORTED = -4 /* valid request that this build does not support */
+};
+
+#define QSIM_MAX_QUBITS 40 /* index arithmetic limit; memory is the practical limit (34 c64 / 33 c128) */
+
+/* Thread-local text of the last error (never NULL; "" when none). */
+const char *qsim_last_error(void);
+/* Library version string. */
+const char *qsim_version(void);
+
+/* ---------------------------------------------------------------------------------------------
+ * State vectors (Sec. II.A, Eq. STAT2; memory 2^n amplitudes, Sec. III.A)
+ * ------------------------------------------------------------------------------------------- */
+
+/* Allocate a state of n qubits (1 <= n <= QSIM_MAX_QUBITS) on the current HIP device and set it to
+ * |0...0>. The library owns the buffer (freed by qsim_free). stream: a hipStream_t, or NULL for the
+ * null stream. Errors: EINVAL (n, dtype, out), ENOMEM (allocation), EDEVICE. */
+int qsim_alloc(int n, int dtype, void *stream, qsim_state **out);
+
+/* Wrap an existing device buffer of 2^n amplitudes (borrowed: not freed by qsim_free; it must stay
+ * alive as long as the state). The contents are left as they are. The buffer must be 16-byte
+ * aligned. Errors: EINVAL. */
+int qsim_wrap(void *dev_ptr, int n, int dtype, void *stream, qsim_state **out);
+
+/* Release the state (and its buffer if the library owns it). NULL is accepted. */
+int qsim_free(qsim_state *s);
+
+/* Device pointer of the amplitudes, qubit count and dtype of a state. */
+void *qsim_data(qsim_state *s);
+int qsim_num_qubits(const qsim_state *s);
+int qsim_get_dtype(const qsim_state *s);
+
+/* Change the HIP stream the state's work is issued on. */
+int qsim_set_stream(qsim_state *s, void *stream);
+
+/* Set the state to the basis state |x> (a_x = 1, all others 0). EINVAL if x >= 2^n. */
+int qsim_set_basis(qsim_state *s, uint64_t x);
+
+/* Copy 2^n amplitudes (bytes must equal 2^n * amplitude size) from host memory into the state /
+ * from the state into host memory. Synchronous. EINVAL on a size mismatch or NULL pointer. */
+int qsim_upload(qsim_state *s, const void *host, size_t bytes);
+int qsim_download(qsim_state *s, void *host, size_t bytes);
+
+/* Wait for all work issued on the state's stream. */
+int qsim_sync(qsim_state *s);
+
+/* ---------------------------------------------------------------------------------------------
+ * Elementary gates (Sec. II.B-II.D; update rules Sec. III.A)
+ * ------------------------------------------------------------------------------------------- */
+
+/* Single-qubit gate U on `target` (Eqs. NUM2-NUM5 are the cases H, X, Y and R(phi)). Touches 2^n
+ * amplitudes; a diagonal U with u00 = 1 touches only the 2^(n-1) amplitudes with bit target = 1
+ * (Eq. NUM5); U = [[0,1],[1,0]] is carried out as a swap with no arithmetic. EINVAL: target out of
+ * range, U NULL. */
+int qsim_apply_1q(qsim_state *s, int target, const double U[8]);
+
+/* Controlled single-qubit gate: U on `target` for the indices whose bits in control_mask are all 1
+ * (CNOT Eq. NUM6, controlled V Eq. NUM7, Toffoli Eq. NUM8 with two control bits; any number of
+ * controls). Touches 2^(n-|C|) amplitudes; permutation matrices are exact swaps (bit-exact).
+ * EINVAL: target out of range, mask >= 2^n or containing the target, U NULL. */
+int qsim_apply_ctrl(qsim_state *s, uint64_t control_mask, int target, const double U[8]);
+
+/* Phase shift R(theta) = diag(1, e^{i theta}) on `target`, controlled by control_mask (Eq. NUM5,
+ * Eq. COMM5). The phase factor cos(theta) + i sin(theta) is evaluated in FP64 on the device
+ * (rounded to FP32 only when applied to a complex64 state). Touches 2^(n-1-|C|) amplitudes. */
+int qsim_apply_phase(qsim_state *s, uint64_t control_mask, int target, double theta);
+
+/* Quantum swap of qubits q0 != q1 (controlled by control_mask): exchanges a(..1_q0..0_q1..) with
+ * a(..0_q0..1_q1..); no arithmetic. Not the paper's data-distribution SWAP command (App. A). */
+int qsim_apply_swap(qsim_state *s, uint64_t control_mask, int q0, int q1);
+
+/* Dense k-qubit gate (1 <= k <= 5, k <= n) on the distinct, possibly unsorted qubits[0..k-1]:
+ * U is 2^k x 2^k complex128, row-major interleaved (re, im), 2^(2k+1) host doubles; matrix index
+ * bit s <-> qubits[s]. For every base index b with zero bits at the k qubits, the 2^k amplitudes
+ * v_r = a(b + sum_s bit_s(r) 2^qubits[s]) are replaced by U v (a generalisation of Eqs. NUM2-NUM8
+ * to k qubits). k >= 4 runs as a dense block contraction on the matrix cores (FP64 MFMA for
+ * complex128, FP32 MFMA with FP32 accumulation for complex64); k <= 3 on the vector ALUs.
+ * EINVAL: k out of range, qubit out of range or repeated, NULL pointers. */
+int qsim_apply_fused(qsim_state *s, int k, const int *qubits, const double *U);
+
+/* ---------------------------------------------------------------------------------------------
+ * Reductions and normalisation (Eq. STAT1; probabilities Sec. II.A; <Q_i> Eq. Shor7)
+ * All accumulate in FP64 for both dtypes.
+ * ------------------------------------------------------------------------------------------- */
+
+/* *out = sum_i |a_i|^2. Deterministic order (fixed grid, tree reductions). Synchronises. */
+int qsim_norm(qsim_state *s, double *out);
+
+/* out[i] = |a_i|^2 in FP64 for i < 2^n. out_is_device != 0: out is a device pointer to 2^n
+ * doubles (asynchronous); otherwise a host pointer (synchronises). */
+int qsim_probs(qsim_state *s, double *out, int out_is_device);
+
+/* Expectation values of the qubit occupation operators, out[q] = sum_k |a_k|^2 bit_q(k) for
+ * q < n (Eq. Shor7), FP64, host pointer to n doubles. Synchronises. */
+int qsim_marginals(qsim_state *s, double *out);
+
+/* Rescale the state to unit norm (Eq. STAT1): a <- a / sqrt(sum |a|^2), the norm and the factor
+ * computed in FP64 on the device. norm_before (may be NULL) receives the norm before rescaling.
+ * EINVAL if the norm is 0. Synchronises. */
+int qsim_renormalize(qsim_state *s, double *norm_before);
+
+/* Draw `shots` basis states with probability |a_x|^2 (Sec. V: sampling of the final state).
+ * uniforms: host array of `shots` doubles in [0, 1) supplied by the caller; out: host array of
+ * `shots` indices. Inverse-CDF sampling over the FP64 cumulative probabilities. Synchronises. */
+int qsim_sample(qsim_state *s, int64_t shots, const double *uniforms, uint64_t *out);
+
+/* ---------------------------------------------------------------------------------------------
+ * Circuits: a gate list lowered once to kernel launches, then executed on any state of that size
+ * ------------------------------------------------------------------------------------------- */
+
+typedef enum {
+    QSIM_OP_MATRIX = 0, /* explicit 2x2 in u[] */
+    QSIM_OP_H,          /* Eq. Hadamard */
+    QSIM_OP_X,          /* Pauli sigma_x (with controls: CNOT Eq. CNOT2, Toffoli Eq. Toffoli) */
+    QSIM_OP_Y,          /* Pauli sigma_y */
+    QSIM_OP_Z,          /* Pauli sigma_z (with a control: CZ) */
+    QSIM_OP_S,          /* diag(1, i) */
+    QSIM_OP_SDG,        /* diag(1, -i) */
+    QSIM_OP_T,          /* diag(1, e^{i pi/4}) */
+    QSIM_OP_TDG,        /* diag(1, e^{-i pi/4}) */
+    QSIM_OP_RX90,       /* the paper's X = exp(i pi S^x/2), Eq. Xoperation */
+    QSIM_OP_RX90DG,     /* its inverse */
+    QSIM_OP_RY90,       /* the paper's Y = exp(i pi S^y/2), Eq. Yoperation */
+    QSIM_OP_RY90DG,     /* its inverse */
+    QSIM_OP_PHASE,      /* R(theta) = diag(1, e^{i theta}), Eq. singlephase (controlled: Eq. COMM5) */
+    QSIM_OP_RZ,         /* diag(e^{-i theta/2}, e^{+i theta/2}) */
+    QSIM_OP_V,          /* V(theta) of Eq. COMM4 (controlled: Eq. NUM7) */
+    QSIM_OP_SWAP,       /* quantum swap of target and target2 */
+    QSIM_OP_COUNT_
+} qsim_op;
+
+typedef struct qsim_gate {
+    int32_t op;        /* qsim_op */
+    int32_t target;    /* target qubit (QSIM_OP_SWAP: first qubit) */
+    int32_t target2;   /* QSIM_OP_SWAP: second qubit; ignored otherwise */
+    int32_t reserved;  /* must be 0 */
+    uint64_t controls; /* control mask */
+    double theta;      /* angle of QSIM_OP_PHASE, QSIM_OP_RZ, QSIM_OP_V */
+    double u[8];       /* QSIM_OP_MATRIX entries, row-major (re, im) */
+} qsim_gate;           /* 96 bytes */
+
+typedef enum {
+    QSIM_PLAN_PLAIN = 0,  /* one in-place sweep per gate (Sec. III.A) */
+    QSIM_PLAN_FUSED = 1,  /* greedy fusion of consecutive gates into dense k-qubit gates */
+    QSIM_PLAN_STAGED = 2, /* LDS-resident blocks: several gates per read/write of the state */
+    QSIM_PLAN_AUTO = 3    /* pick the fastest of the above from the tuning table */
+} qsim_plan_method;
+
+typedef struct qsim_plan_opts {
+    int32_t method;     /* qsim_plan_method */
+    int32_t fuse_k;     /* QSIM_PLAN_FUSED: largest fused width, 1..5 (0 = 5) */
+    int32_t lds_qubits; /* QSIM_PLAN_STAGED: qubits resident per LDS block (0 = default) */
+    int32_t use_graph;  /* nonzero: record the launch sequence in a HIP graph on the first execute
+                           and replay it afterwards (per state) */
+} qsim_plan_opts;
+
+typedef struct qsim_plan_info {
+    int64_t gates;          /* gates of the original circuit */
+    int64_t launches;       /* kernel launches per execute */
+    int64_t passes;         /* launches that read and write the whole state */
+    double alg_bytes;       /* algorithmic HBM bytes per execute (per state) */
+    double alg_flops;       /* algorithmic flops of the fused contractions per execute */
+    int32_t method;         /* method actually used */
+    int32_t fuse_k;         /* fused width used (QSIM_PLAN_FUSED) */
+    int32_t lds_qubits;     /* resident qubits used (QSIM_PLAN_STAGED) */
+    int32_t reserved;
+} qsim_plan_info;
+
+/* Lower `ngates` gates for states of n qubits and the given dtype. The gate list is copied.
+ * EINVAL on a malformed gate (qubit range, mask, op code) or options. */
+int qsim_plan_create(int n, int dtype, const qsim_gate *gates, int64_t ngates, const qsim_plan_opts *opts,
+                     qsim_plan **out);
+int qsim_plan_get_info(const qsim_plan *p, qsim_plan_info *info);
+/* Apply the plan to the state (asynchronous on its stream). EINVAL if n or dtype differ. */
+int qsim_plan_execute(qsim_plan *p, qsim_state *s);
+int qsim_plan_free(qsim_plan *p);
+
+/* Kernel classes reported by qsim_plan_execute_timed. */
+enum {
+    QSIM_KERNEL_GENERAL = 0,    /* 2x2 pair sweep (Eqs. NUM2-NUM4, NUM7) */
+    QSIM_KERNEL_PHASE = 1,      /* phase on the |1> amplitudes (Eq. NUM5, Eq. COMM5) */
+    QSIM_KERNEL_DIAG = 2,       /* diagonal 2x2 on every amplitude */
+    QSIM_KERNEL_SWAP = 3,       /* permutation (Eqs. NUM6, NUM8, quantum swap) */
+    QSIM_KERNEL_FUSED_VALU = 4, /* dense k <= 3 gate on the vector ALUs */
+    QSIM_KERNEL_FUSED_MFMA = 5, /* dense k = 4, 5 gate on the matrix cores */
+    QSIM_KERNEL_STAGED = 6      /* LDS-resident multi-gate pass */
+};
+
+/* Execute like qsim_plan_execute (never through a graph) with a pair of HIP events recorded on the
+ * state's stream around every launch, then synchronise. launch_ms[i] receives the duration of
+ * launch i and kind[i] its QSIM_KERNEL_* class, fused_k[i] the fused width (0 if none); each array
+ * needs info.launches entries and may be NULL. */
+int qsim_plan_execute_timed(qsim_plan *p, qsim_state *s, double *launch_ms, int32_t *kind, int32_t *fused_k);
+
+/* ---------------------------------------------------------------------------------------------
+ * Batches of independent small circuits in one persistent launch
+ * ------------------------------------------------------------------------------------------- */
+
+typedef struct qsim_batch qsim_batch; /* opaque */
+
+typedef struct qsim_batch_stats {
+    double launch_ms;       /* wall time of the launch, HIP events */
+    int64_t circuits;
+    int64_t gates;
+} qsim_batch_stats;
+
+/* Build a batch of `count` circuits for one dtype: circuit c has nqubits[c] qubits (1..24) and the
+ * gates gates[offsets[c] .. offsets[c+1]-1]; every circuit starts from |0...0>. The gate tables
+ * and the state pool are placed in device memory (owned by the batch).
+ * EINVAL on malformed input, ENOMEM if the pool does not fit. */
+int qsim_batch_create(int count, const int *nqubits, const int64_t *offsets, const qsim_gate *gates, int dtype,
+                      void *stream, qsim_batch **out);
+/* Run every circuit of the batch from |0...0> in one persistent kernel launch. stats may be NULL.
+ * Per-circuit device timestamps (claim -> finish, in device clock ticks) are kept for
+ * qsim_batch_latencies. Synchronises. */
+int qsim_batch_run(qsim_batch *b, qsim_batch_stats *stats);
+/* Per-circuit latencies of the last run in microseconds (host array of count doubles). */
+int qsim_batch_latencies(qsim_batch *b, double *out_us);
+/* Copy circuit c's final state (2^nqubits[c] amplitudes) to host memory. */
+int qsim_batch_download(qsim_batch *b, int c, void *host, size_t bytes);
+int qsim_batch_free(qsim_batch *b);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* QSIM_H */

@@ -69,13 +69,19 @@ def lib():
             "or_probs": [dp, i32, dp],
             "or_norm": [dp, i32],
             "or_marginals": [dp, i32, dp],
+            "or_threads": [],
         }
         for name, args in sigs.items():
             f = getattr(L, name)
             f.argtypes = args
-            f.restype = f64 if name == "or_norm" else None
+            f.restype = f64 if name == "or_norm" else (i32 if name == "or_threads" else None)
         _lib = L
     return _lib
+
+
+def threads() -> int:
+    """OpenMP threads the oracle's loops use on this host."""
+    return int(lib().or_threads())
 
 
 def _dp(x: np.ndarray):

@@ -18,6 +18,20 @@
 #include <stdlib.h>
 #include <string.h>
 
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* Threads the OpenMP loops use (1 without OpenMP). */
+int or_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
 #define BIT(i, q) (((i) >> (q)) & 1ULL)
 
 /* Eq. NUM2: Hadamard on qubit j. a'(..0_j..) = (a(..0_j..) + a(..1_j..))/sqrt2,

@@ -1,0 +1,421 @@
+// Circuit plans: a gate list lowered once to a sequence of launches, then executed on any state of
+// the same size and dtype.
+//   PLAIN  - one sweep per gate (the paper's execution model, Sec. III.A).
+//   FUSED  - greedy fusion: consecutive gates are merged while the union of their qubits has at
+//            most k members; each merged block becomes one dense k-qubit gate whose 2^k x 2^k
+//            matrix is the ordered product of the embedded gates, formed in FP64 on the host.
+//            Matrices of blocks with k >= 4 are staged once in device memory in the fragment order
+//            of the matrix-core kernel.
+//   STAGED - LDS-resident passes (see staged.hip).
+// With use_graph the launch sequence of a plan is recorded once per state in a HIP graph.
+#include <algorithm>
+#include <climits>
+#include <cstdint>
+#include <atomic>
+#include <cmath>
+#include <complex>
+#include <cstring>
+
+#include "qsim_internal.h"
+
+namespace qsim {
+
+size_t wfrag_bytes(int k, int dtype);
+int build_wfrag_host(int k, int dtype, const double *U, void *host_out);
+int launch_fused_mfma(qsim_state *s, int k, const int *qubits, const void *dev_wfrag);
+int launch_fused_valu(qsim_state *s, int k, const int *qubits, const double *U);
+
+struct StagedPlan;  // staged.hip
+int staged_build(int n, int dtype, const std::vector<qsim_gate> &gates, int lds_qubits, StagedPlan **out, qsim_plan_info *info);
+int staged_execute(StagedPlan *p, qsim_state *s);
+int staged_execute_timed(StagedPlan *p, qsim_state *s, double *ms, int32_t *kind, int32_t *fk);
+void staged_free(StagedPlan *p);
+
+}  // namespace qsim
+
+using namespace qsim;
+
+namespace {
+
+std::atomic<uint64_t> g_plan_ids{1};
+
+struct Step {
+    int type = 0;  // 0 = single gate, 1 = fused
+    qsim_gate g{};
+    int k = 0;
+    int qubits[5] = {0, 0, 0, 0, 0};
+    size_t wofs = 0;          // fused k >= 4: byte offset into the device W table
+    std::vector<double> U;    // fused k <= 3: complex row-major
+};
+
+// qubits a gate touches (targets and controls)
+uint64_t gate_qubits(const qsim_gate &g)
+{
+    uint64_t m = g.controls | (uint64_t(1) << g.target);
+    if (g.op == QSIM_OP_SWAP) m |= uint64_t(1) << g.target2;
+    return m;
+}
+
+// algorithmic amplitudes touched by one sweep of the gate (read and written once each)
+double touched(const qsim_gate &g, int n)
+{
+    const int nc = __builtin_popcountll(g.controls);
+    const double full = std::ldexp(1.0, n - nc);
+    if (g.op == QSIM_OP_SWAP) return full / 2;
+    if (g.op == QSIM_OP_PHASE) return full / 2;
+    double u[8];
+    if (gate_matrix(g, u)) return full;
+    if (classify(u) == Kind::Phase1) return full / 2;
+    return full;
+}
+
+using cd = std::complex<double>;
+
+// apply one gate to the 2^m x 2^m matrix M (columns = basis inputs) over the block's local qubits
+void embed_apply(std::vector<cd> &M, int m, const std::vector<int> &local_of, const qsim_gate &g)
+{
+    const int D = 1 << m;
+    auto loc = [&](int q) { return local_of[q]; };
+    uint64_t lc = 0;
+    for (int q = 0; q < 64; ++q)
+        if ((g.controls >> q) & 1) lc |= uint64_t(1) << loc(q);
+    if (g.op == QSIM_OP_SWAP) {
+        const int p0 = loc(g.target), p1 = loc(g.target2);
+        for (int c = 0; c < D; ++c)
+            for (int r = 0; r < D; ++r) {
+                if ((uint64_t(r) & lc) != lc) continue;
+                if (((r >> p0) & 1) == 1 && ((r >> p1) & 1) == 0) {
+                    const int r2 = (r & ~(1 << p0)) | (1 << p1);
+                    std::swap(M[size_t(r) * D + c], M[size_t(r2) * D + c]);
+                }
+            }
+        return;
+    }
+    double u[8];
+    gate_matrix(g, u);
+    const cd u00(u[0], u[1]), u01(u[2], u[3]), u10(u[4], u[5]), u11(u[6], u[7]);
+    const int t = loc(g.target);
+    for (int c = 0; c < D; ++c)
+        for (int r = 0; r < D; ++r) {
+            if ((r >> t) & 1) continue;
+            if ((uint64_t(r) & lc) != lc) continue;
+            const int r1 = r | (1 << t);
+            const cd x0 = M[size_t(r) * D + c], x1 = M[size_t(r1) * D + c];
+            M[size_t(r) * D + c] = u00 * x0 + u01 * x1;
+            M[size_t(r1) * D + c] = u10 * x0 + u11 * x1;
+        }
+}
+
+}  // namespace
+
+struct qsim_plan {
+    uint64_t id = 0;
+    int n = 0, dtype = 0;
+    qsim_plan_opts opts{};
+    qsim_plan_info info{};
+    std::vector<Step> steps;
+    void *dev_w = nullptr;  // device W table for fused k >= 4
+    StagedPlan *staged = nullptr;
+};
+
+namespace qsim {
+
+// Greedy fusion over the gate dependency order: a gate is ready when every earlier gate that shares
+// a qubit with it has been placed. A block starts from the earliest ready gate and keeps absorbing
+// ready gates (earliest first, gates inside the block's qubit set before ones that widen it) while
+// the union of qubits stays within kmax. Gates are applied inside a block in the order they were
+// absorbed, which respects every dependency, so the block matrix is the exact product.
+static int build_fused(qsim_plan *p, const std::vector<qsim_gate> &gates, int kmax)
+{
+    const int n = p->n;
+    // blocks of 4-5 qubits need n >= k + 4 for the matrix-core tiling
+    while (kmax >= 4 && n < kmax + 4) --kmax;
+    p->info.fuse_k = kmax;
+    const size_t G = gates.size();
+    std::vector<unsigned char> wtable;
+    std::vector<uint64_t> gq(G);
+    for (size_t i = 0; i < G; ++i) gq[i] = gate_qubits(gates[i]);
+    // per-qubit ordered gate lists and front pointers
+    std::vector<std::vector<uint32_t>> onq(64);
+    for (size_t i = 0; i < G; ++i)
+        for (int q = 0; q < 64; ++q)
+            if ((gq[i] >> q) & 1) onq[q].push_back(uint32_t(i));
+    std::vector<size_t> front(64, 0);
+    std::vector<char> done(G, 0);
+    auto ready = [&](size_t i) {
+        for (int q = 0; q < 64; ++q)
+            if ((gq[i] >> q) & 1)
+                if (front[q] >= onq[q].size() || onq[q][front[q]] != i) return false;
+        return true;
+    };
+    auto place = [&](size_t i) {
+        done[i] = 1;
+        for (int q = 0; q < 64; ++q)
+            if ((gq[i] >> q) & 1) ++front[q];
+    };
+    size_t first = 0;  // earliest gate not yet placed
+    while (true) {
+        while (first < G && done[first]) ++first;
+        if (first >= G) break;
+        const size_t g0 = first;  // the earliest unplaced gate is always ready
+        std::vector<size_t> members{g0};
+        uint64_t Q = gq[g0];
+        place(g0);
+        if (__builtin_popcountll(Q) <= kmax) {
+            bool grew = true;
+            while (grew) {
+                grew = false;
+                // candidates: the front gate of every qubit (ready gates only)
+                size_t best = SIZE_MAX;
+                bool best_inside = false;
+                for (int q = 0; q < n; ++q) {
+                    if (front[q] >= onq[q].size()) continue;
+                    const size_t c = onq[q][front[q]];
+                    if (done[c] || !ready(c)) continue;
+                    const uint64_t U2 = Q | gq[c];
+                    if (__builtin_popcountll(U2) > kmax) continue;
+                    const bool inside = U2 == Q;
+                    if (best == SIZE_MAX || (inside && !best_inside) || (inside == best_inside && c < best)) {
+                        best = c;
+                        best_inside = inside;
+                    }
+                }
+                if (best != SIZE_MAX) {
+                    members.push_back(best);
+                    Q |= gq[best];
+                    place(best);
+                    grew = true;
+                }
+            }
+        }
+        if (members.size() == 1) {  // a block of one gate keeps its specialised sweep
+            Step st;
+            st.g = gates[g0];
+            p->steps.push_back(st);
+            p->info.alg_bytes += 2.0 * touched(gates[g0], n) * amp_bytes(p->dtype);
+            continue;
+        }
+        std::vector<int> qs;
+        for (int q = 0; q < n; ++q)
+            if ((Q >> q) & 1) qs.push_back(q);
+        const int m = int(qs.size());
+        std::vector<int> local_of(64, -1);
+        for (int s = 0; s < m; ++s) local_of[qs[s]] = s;
+        const int D = 1 << m;
+        std::vector<cd> M(size_t(D) * D, cd(0, 0));
+        for (int d = 0; d < D; ++d) M[size_t(d) * D + d] = cd(1, 0);
+        for (size_t g : members) embed_apply(M, m, local_of, gates[g]);
+        Step st;
+        st.type = 1;
+        st.k = m;
+        for (int s = 0; s < m; ++s) st.qubits[s] = qs[s];
+        std::vector<double> U(size_t(2) * D * D);
+        for (size_t e = 0; e < size_t(D) * D; ++e) {
+            U[2 * e] = M[e].real();
+            U[2 * e + 1] = M[e].imag();
+        }
+        const bool mfma = m >= 4 && n >= m + 4;
+        if (mfma) {
+            const size_t bytes = wfrag_bytes(m, p->dtype);
+            st.wofs = wtable.size();
+            wtable.resize(wtable.size() + bytes);
+            build_wfrag_host(m, p->dtype, U.data(), wtable.data() + st.wofs);
+            p->info.alg_flops += 8.0 * std::ldexp(1.0, n + m);
+        } else if (m <= 3) {
+            st.U = std::move(U);
+        } else {
+            return set_error(QSIM_EUNSUPPORTED, "fused: block of 4-5 qubits needs n >= k + 4");
+        }
+        p->steps.push_back(std::move(st));
+        p->info.alg_bytes += 2.0 * std::ldexp(1.0, n) * amp_bytes(p->dtype);
+    }
+    if (!wtable.empty()) {
+        QSIM_HIP(hipMalloc(&p->dev_w, wtable.size()));
+        QSIM_HIP(hipMemcpy(p->dev_w, wtable.data(), wtable.size(), hipMemcpyHostToDevice));
+    }
+    return QSIM_OK;
+}
+
+static int kernel_kind(const Step &st)
+{
+    if (st.type == 1) return st.k >= 4 ? QSIM_KERNEL_FUSED_MFMA : QSIM_KERNEL_FUSED_VALU;
+    const qsim_gate &g = st.g;
+    if (g.op == QSIM_OP_SWAP) return QSIM_KERNEL_SWAP;
+    if (g.op == QSIM_OP_PHASE) return QSIM_KERNEL_PHASE;
+    if (g.op == QSIM_OP_RZ) return QSIM_KERNEL_DIAG;
+    double u[8];
+    if (gate_matrix(g, u)) return QSIM_KERNEL_GENERAL;
+    switch (classify(u)) {
+    case Kind::Swap: return QSIM_KERNEL_SWAP;
+    case Kind::Phase1: return QSIM_KERNEL_PHASE;
+    case Kind::Diag: return QSIM_KERNEL_DIAG;
+    default: return QSIM_KERNEL_GENERAL;
+    }
+}
+
+static int run_step(qsim_plan *p, qsim_state *s, const Step &st)
+{
+    if (st.type == 0) return apply_gate_record(s, st.g);
+    if (st.k >= 4) return launch_fused_mfma(s, st.k, st.qubits, static_cast<unsigned char *>(p->dev_w) + st.wofs);
+    return launch_fused_valu(s, st.k, st.qubits, st.U.data());
+}
+
+static int run_steps_timed(qsim_plan *p, qsim_state *s, double *ms, int32_t *kind, int32_t *fk)
+{
+    if (p->staged) return staged_execute_timed(p->staged, s, ms, kind, fk);
+    const size_t L = p->steps.size();
+    std::vector<hipEvent_t> ev(2 * L, nullptr);
+    for (auto &e : ev) QSIM_HIP(hipEventCreate(&e));
+    int rc = QSIM_OK;
+    for (size_t i = 0; i < L && !rc; ++i) {
+        QSIM_HIP(hipEventRecord(ev[2 * i], s->stream));
+        rc = run_step(p, s, p->steps[i]);
+        QSIM_HIP(hipEventRecord(ev[2 * i + 1], s->stream));
+    }
+    if (!rc) {
+        QSIM_HIP(hipStreamSynchronize(s->stream));
+        for (size_t i = 0; i < L; ++i) {
+            float t = 0.f;
+            QSIM_HIP(hipEventElapsedTime(&t, ev[2 * i], ev[2 * i + 1]));
+            if (ms) ms[i] = t;
+            if (kind) kind[i] = kernel_kind(p->steps[i]);
+            if (fk) fk[i] = p->steps[i].type == 1 ? p->steps[i].k : 0;
+        }
+    }
+    for (auto &e : ev) (void)hipEventDestroy(e);
+    return rc;
+}
+
+static int run_steps(qsim_plan *p, qsim_state *s)
+{
+    if (p->staged) return staged_execute(p->staged, s);
+    for (const Step &st : p->steps) {
+        int rc;
+        if (st.type == 0)
+            rc = apply_gate_record(s, st.g);
+        else if (st.k >= 4)
+            rc = launch_fused_mfma(s, st.k, st.qubits, static_cast<unsigned char *>(p->dev_w) + st.wofs);
+        else
+            rc = launch_fused_valu(s, st.k, st.qubits, st.U.data());
+        if (rc) return rc;
+    }
+    return QSIM_OK;
+}
+
+}  // namespace qsim
+
+extern "C" {
+
+int qsim_plan_create(int n, int dtype, const qsim_gate *gates, int64_t ngates, const qsim_plan_opts *opts, qsim_plan **out)
+{
+    if (!out) return set_error(QSIM_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (n < 1 || n > QSIM_MAX_QUBITS) return set_error(QSIM_EINVAL, "n out of range");
+    if (dtype != QSIM_C64 && dtype != QSIM_C128) return set_error(QSIM_EINVAL, "unknown dtype");
+    if (ngates < 0 || (ngates > 0 && !gates)) return set_error(QSIM_EINVAL, "gates is NULL");
+    qsim_plan_opts o{};
+    if (opts) o = *opts;
+    if (o.method < QSIM_PLAN_PLAIN || o.method > QSIM_PLAN_AUTO) return set_error(QSIM_EINVAL, "unknown plan method");
+    if (o.fuse_k == 0) o.fuse_k = 5;
+    if (o.fuse_k < 1 || o.fuse_k > 5) return set_error(QSIM_EINVAL, "fuse_k out of range (1..5)");
+    std::vector<qsim_gate> gl(gates, gates + ngates);
+    for (const qsim_gate &g : gl)
+        if (int rc = validate_gate(g, n)) return rc;
+    if (o.method == QSIM_PLAN_AUTO) o.method = QSIM_PLAN_FUSED;  // replaced by the tuner's choice below
+    qsim_plan *p = new qsim_plan();
+    p->id = g_plan_ids.fetch_add(1);
+    p->n = n;
+    p->dtype = dtype;
+    p->opts = o;
+    p->info.gates = ngates;
+    p->info.method = o.method;
+    int rc = QSIM_OK;
+    if (o.method == QSIM_PLAN_PLAIN) {
+        for (const qsim_gate &g : gl) {
+            Step st;
+            st.g = g;
+            p->steps.push_back(st);
+            p->info.alg_bytes += 2.0 * touched(g, n) * amp_bytes(dtype);
+        }
+    } else if (o.method == QSIM_PLAN_FUSED) {
+        rc = build_fused(p, gl, o.fuse_k);
+    } else {
+        rc = staged_build(n, dtype, gl, o.lds_qubits, &p->staged, &p->info);
+    }
+    if (rc) {
+        qsim_plan_free(p);
+        return rc;
+    }
+    if (!p->staged) {
+        p->info.launches = int64_t(p->steps.size());
+        int64_t passes = 0;
+        for (const Step &st : p->steps) passes += (st.type == 1) || touched(st.g, n) >= std::ldexp(1.0, n);
+        p->info.passes = passes;
+    }
+    *out = p;
+    return QSIM_OK;
+}
+
+int qsim_plan_get_info(const qsim_plan *p, qsim_plan_info *info)
+{
+    if (!p || !info) return set_error(QSIM_EINVAL, "null argument");
+    *info = p->info;
+    return QSIM_OK;
+}
+
+int qsim_plan_execute(qsim_plan *p, qsim_state *s)
+{
+    if (!p || !s || !s->data) return set_error(QSIM_EINVAL, "null argument");
+    if (p->n != s->n || p->dtype != s->dtype) return set_error(QSIM_EINVAL, "plan and state differ in n or dtype");
+    if (!p->opts.use_graph || s->stream == nullptr) return run_steps(p, s);
+    if (s->graph_exec && s->graph_plan == reinterpret_cast<const void *>(p->id)) {
+        QSIM_HIP(hipGraphLaunch(s->graph_exec, s->stream));
+        return QSIM_OK;
+    }
+    if (s->graph_exec) {
+        hipGraphExecDestroy(s->graph_exec);
+        s->graph_exec = nullptr;
+    }
+    if (s->graph) {
+        hipGraphDestroy(s->graph);
+        s->graph = nullptr;
+    }
+    QSIM_HIP(hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal));
+    int rc = run_steps(p, s);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(s->stream, &g);
+    if (rc) {
+        if (g) hipGraphDestroy(g);
+        return rc;
+    }
+    if (e != hipSuccess) return hip_error(e, "hipStreamEndCapture");
+    hipGraphExec_t ge = nullptr;
+    e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        hipGraphDestroy(g);
+        return hip_error(e, "hipGraphInstantiate");
+    }
+    s->graph = g;
+    s->graph_exec = ge;
+    s->graph_plan = reinterpret_cast<const void *>(p->id);
+    QSIM_HIP(hipGraphLaunch(ge, s->stream));
+    return QSIM_OK;
+}
+
+int qsim_plan_execute_timed(qsim_plan *p, qsim_state *s, double *launch_ms, int32_t *kind, int32_t *fused_k)
+{
+    if (!p || !s || !s->data) return set_error(QSIM_EINVAL, "null argument");
+    if (p->n != s->n || p->dtype != s->dtype) return set_error(QSIM_EINVAL, "plan and state differ in n or dtype");
+    return run_steps_timed(p, s, launch_ms, kind, fused_k);
+}
+
+int qsim_plan_free(qsim_plan *p)
+{
+    if (!p) return QSIM_OK;
+    if (p->dev_w) hipFree(p->dev_w);
+    if (p->staged) staged_free(p->staged);
+    delete p;
+    return QSIM_OK;
+}
+
+}  // extern "C"

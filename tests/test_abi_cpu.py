@@ -1,0 +1,121 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads, exports every function that
+include/qsim.h declares, the Python binding declares the same set, and argument validation rejects
+bad input before anything touches the device."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "qsim.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = set(re.findall(r"\b(qsim_[a-z0-9_]+)\s*\(", src))
+    return sorted(names)
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_quant_ph_0608239_amd import _lib
+    return _lib.lib()
+
+
+def test_header_declares_the_north_star_calls():
+    names = declared_functions()
+    for must in ["qsim_alloc", "qsim_apply_1q", "qsim_apply_ctrl", "qsim_apply_fused", "qsim_probs", "qsim_norm"]:
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol(L):
+    out = subprocess.run(["nm", "-D", "--defined-only", os.path.join(ROOT, "paper_quant_ph_0608239_amd", "libqsim.so")],
+                         capture_output=True, text=True, check=True).stdout
+    exported = set(re.findall(r"\bT (qsim_[a-z0-9_]+)", out))
+    missing = [n for n in declared_functions() if n not in exported]
+    assert not missing, missing
+    for n in declared_functions():
+        assert hasattr(L, n)
+
+
+def test_binding_covers_header():
+    from paper_quant_ph_0608239_amd import _lib
+    assert sorted(_lib.SIGNATURES) == declared_functions()
+
+
+def test_gate_struct_layout():
+    from paper_quant_ph_0608239_amd import _lib
+    assert ctypes.sizeof(_lib.Gate) == 96
+    assert ctypes.sizeof(_lib.PlanInfo) == 56
+
+
+def _plan(L, n, gates, method=0, dtype=1):
+    from paper_quant_ph_0608239_amd import _lib
+    arr = (_lib.Gate * max(1, len(gates)))(*gates)
+    opts = _lib.PlanOpts(method, 5, 0, 0)
+    h = ctypes.c_void_p()
+    rc = L.qsim_plan_create(n, dtype, arr, len(gates), ctypes.byref(opts), ctypes.byref(h))
+    return rc, h
+
+
+def _g(op, t, controls=0, t2=-1, theta=0.0):
+    from paper_quant_ph_0608239_amd import _lib
+    g = _lib.Gate()
+    g.op, g.target, g.target2, g.controls, g.theta = _lib.OPS[op], t, t2, controls, theta
+    return g
+
+
+def test_validation_rejects_before_device(L):
+    from paper_quant_ph_0608239_amd import _lib
+    h = ctypes.c_void_p()
+    assert L.qsim_alloc(0, 1, None, ctypes.byref(h)) == _lib.EINVAL
+    assert L.qsim_alloc(41, 1, None, ctypes.byref(h)) == _lib.EINVAL
+    assert L.qsim_alloc(4, 7, None, ctypes.byref(h)) == _lib.EINVAL
+    assert L.qsim_wrap(None, 4, 1, None, ctypes.byref(h)) == _lib.EINVAL
+    assert L.qsim_wrap(ctypes.c_void_p(8), 4, 1, None, ctypes.byref(h)) == _lib.EINVAL  # misaligned
+    assert L.qsim_norm(None, None) == _lib.EINVAL
+    assert b"null" in L.qsim_last_error()
+    for bad in [_g("H", 4), _g("X", 1, controls=0b10), _g("X", 0, controls=1 << 4),
+                _g("SWAP", 1, t2=1), _g("SWAP", 1, t2=9), _g("PHASE", 0, theta=float("nan"))]:
+        rc, _ = _plan(L, 4, [bad])
+        assert rc == _lib.EINVAL, (bad.op, bad.target)
+    g = _g("H", 0)
+    g.op = 99
+    assert _plan(L, 4, [g])[0] == _lib.EINVAL
+
+
+def test_plain_plan_bookkeeping(L):
+    """Plain plans need no device: one launch per gate, algorithmic bytes by the paper's work model
+    (Sec. III.A: 2^n amplitudes for a single-qubit gate, 2^(n-1) for a phase shift, 2^(n-1) for a
+    CNOT, 2^(n-2) for a Toffoli)."""
+    from paper_quant_ph_0608239_amd import _lib
+    n = 10
+    gates = [_g("H", 3), _g("PHASE", 2, theta=0.5), _g("X", 5, controls=1 << 1), _g("X", 7, controls=0b11),
+             _g("Z", 4, controls=1 << 6), _g("SWAP", 0, t2=9)]
+    rc, h = _plan(L, n, gates)
+    assert rc == 0
+    info = _lib.PlanInfo()
+    assert L.qsim_plan_get_info(h, ctypes.byref(info)) == 0
+    assert info.launches == len(gates) and info.gates == len(gates)
+    amps = [2 ** n, 2 ** (n - 1), 2 ** (n - 1), 2 ** (n - 2), 2 ** (n - 2), 2 ** (n - 1)]
+    assert info.alg_bytes == 2 * 16 * sum(amps)
+    L.qsim_plan_free(h)
+
+
+def test_circuit_parser_maps_keywords():
+    import qsim_workloads as wl
+    from paper_quant_ph_0608239_amd import parse_circuit, _lib
+    text = wl.circuit_text(5, ["H 0", "CNOT 0 1", "TOFFOLI 0 1 2", "CRK 1 3 4", "CRKDG 1 3 4", "QSWAP 0 4",
+                               "CV 2 3 0x1.8p+0", "RZ 4 0.5", "U 2 1 0 0 0 0 0 1 0"], initial_state=3)
+    c = parse_circuit(text)
+    assert c.n == 5 and c.init == 3 and len(c.gates) == 9
+    g = c.gates
+    assert (g[1].op, g[1].target, g[1].controls) == (_lib.OPS["X"], 1, 1)
+    assert (g[2].op, g[2].target, g[2].controls) == (_lib.OPS["X"], 2, 3)
+    assert g[3].op == _lib.OPS["PHASE"] and g[3].theta == 2 * 3.141592653589793 / 16 and g[3].controls == 2
+    assert g[4].theta == -g[3].theta
+    assert (g[5].op, g[5].target, g[5].target2) == (_lib.OPS["SWAP"], 0, 4)
+    assert g[6].theta == 1.5 and g[7].theta == 0.5 and list(g[8].u) == [1, 0, 0, 0, 0, 0, 1, 0]

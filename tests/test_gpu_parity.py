@@ -1,0 +1,329 @@
+"""GPU parity: every C-ABI call of libqsim against the FP64 CPU oracle on the same seeded inputs.
+
+Bars: permutation work (X, CNOT, Toffoli, quantum swap, adders on basis states) is bit-exact;
+complex128 results are within max|d amp| <= 1e-12 of the oracle; complex64 single-gate results
+within 2e-6 and circuit results within 1 - F <= 1e-6 of the FP64 oracle.
+"""
+import itertools
+import math
+
+import numpy as np
+import pytest
+
+import qsim_workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+TOL128 = 1e-12
+TOL64_GATE = 2e-6
+TOL64_FID = 1e-6
+
+
+@pytest.fixture(scope="module")
+def q():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_quant_ph_0608239_amd as q
+    q.lib()
+    return q
+
+
+def gpu_state(q, psi, dtype):
+    n = int(round(math.log2(psi.size)))
+    s = q.State(n, dtype)
+    s.upload(psi)
+    return s
+
+
+def oracle_line(oracle_mod, psi, line):
+    n = int(round(math.log2(psi.size)))
+    return oracle_mod.run_circuit(wl.circuit_text(n, [line]), psi0=psi)
+
+
+def u_line_args(U):
+    return " ".join(float(v).hex() for v in np.asarray(U, np.complex128).reshape(-1).view(np.float64))
+
+
+def check(got, want, dtype, what=""):
+    got = np.asarray(got, np.complex128)
+    d = np.max(np.abs(got - want)) if got.size else 0.0
+    tol = TOL128 if dtype == "c128" else TOL64_GATE
+    assert d <= tol, f"{what}: max|d| = {d:.3e} > {tol}"
+
+
+DTYPES = ["c128", "c64"]
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("n", [1, 2, 3, 5, 8, 11])
+def test_apply_1q_every_target(q, oracle_mod, dtype, n):
+    rng = np.random.default_rng(1000 + n)
+    psi = wl.gaussian_state(n, 77 + n)
+    s = gpu_state(q, psi, dtype)
+    ref = psi.copy()
+    for t in range(n):
+        U = wl.haar_2x2(rng)
+        s.apply_1q(t, U)
+        ref = oracle_line(oracle_mod, ref, f"U {t} {u_line_args(U)}")
+    check(s.download(), ref, dtype, f"n={n}")
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_apply_1q_specialised_forms(q, oracle_mod, dtype):
+    """Diagonal (Eq. NUM5 form and general diag), X as a swap, identity: the classified paths."""
+    n = 9
+    rng = np.random.default_rng(5)
+    psi = wl.gaussian_state(n, 5)
+    s = gpu_state(q, psi, dtype)
+    ref = psi.copy()
+    mats = [np.diag([1, np.exp(0.3j)]), np.diag([np.exp(-0.7j), np.exp(1.1j)]), np.array([[0, 1], [1, 0]]),
+            np.eye(2), np.array([[0, -1j], [1j, 0]])]
+    for t in [0, 1, 4, 8]:
+        for U in mats:
+            s.apply_1q(t, U)
+            ref = oracle_line(oracle_mod, ref, f"U {t} {u_line_args(U)}")
+    check(s.download(), ref, dtype)
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("n", [3, 6, 10])
+def test_apply_ctrl_targets_and_control_sets(q, oracle_mod, dtype, n):
+    rng = np.random.default_rng(2000 + n)
+    psi = wl.gaussian_state(n, 88 + n)
+    s = gpu_state(q, psi, dtype)
+    ref = psi.copy()
+    for t in range(n):
+        others = [x for x in range(n) if x != t]
+        for nc in range(1, min(3, n - 1) + 1):
+            sets = list(itertools.combinations(others, nc))
+            rng.shuffle(sets)
+            for C in sets[:3]:
+                U = wl.haar_2x2(rng)
+                mask = sum(1 << c for c in C)
+                s.apply_ctrl(mask, t, U)
+                a = oracle_mod.to_interleaved(ref)
+                oracle_mod.lib().or_unitary(oracle_mod._dp(a), n, t, mask, oracle_mod._dp(oracle_mod._u8(U)))
+                ref = oracle_mod.to_complex(a).copy()
+    check(s.download(), ref, dtype, f"n={n}")
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_permutations_bit_exact(q, oracle_mod, dtype):
+    """CNOT, Toffoli, 3-control X and quantum swaps move amplitudes without arithmetic."""
+    n = 11
+    psi = wl.gaussian_state(n, 9)
+    if dtype == "c64":
+        psi = psi.astype(np.complex64).astype(np.complex128)  # exactly representable input
+    s = gpu_state(q, psi, dtype)
+    ref = psi.copy()
+    X = np.array([[0, 1], [1, 0]])
+    rng = np.random.default_rng(3)
+    for _ in range(40):
+        k = int(rng.integers(0, 4))
+        qs = [int(x) for x in rng.permutation(n)[:k + 1]]
+        t, C = qs[0], qs[1:]
+        mask = sum(1 << c for c in C)
+        s.apply_ctrl(mask, t, X)
+        a = oracle_mod.to_interleaved(ref)
+        oracle_mod.lib().or_cnot(oracle_mod._dp(a), n, mask, t)
+        ref = oracle_mod.to_complex(a).copy()
+        a0, b0 = [int(x) for x in rng.permutation(n)[:2]]
+        s.apply_swap(a0, b0)
+        ref = oracle_line(oracle_mod, ref, f"QSWAP {a0} {b0}")
+    got = s.download().astype(np.complex128)
+    assert np.array_equal(got, ref)
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_apply_phase_device_angles(q, oracle_mod, dtype):
+    n = 10
+    psi = wl.gaussian_state(n, 21)
+    s = gpu_state(q, psi, dtype)
+    ref = psi.copy()
+    rng = np.random.default_rng(4)
+    for t in range(n):
+        for nc in range(0, 3):
+            C = [int(x) for x in rng.permutation([x for x in range(n) if x != t])[:nc]]
+            mask = sum(1 << c for c in C)
+            th = float(rng.uniform(0, 2 * np.pi))
+            s.apply_phase(mask, t, th)
+            a = oracle_mod.to_interleaved(ref)
+            oracle_mod.lib().or_phase(oracle_mod._dp(a), n, t, mask, th)
+            ref = oracle_mod.to_complex(a).copy()
+    check(s.download(), ref, dtype)
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("n,k", [(3, 1), (5, 2), (7, 3), (8, 4), (9, 5), (12, 4), (12, 5), (16, 5), (17, 3)])
+def test_apply_fused_unsorted_qubits(q, oracle_mod, dtype, n, k):
+    rng = np.random.default_rng(3000 + 10 * n + k)
+    psi = wl.gaussian_state(n, 31 + n)
+    s = gpu_state(q, psi, dtype)
+    ref = psi.copy()
+    for rep in range(3):
+        qubits = [int(x) for x in rng.permutation(n)[:k]]
+        if rep == 0:
+            qubits = sorted(qubits)
+        Z = rng.standard_normal((2 ** k, 2 ** k)) + 1j * rng.standard_normal((2 ** k, 2 ** k))
+        U, _ = np.linalg.qr(Z)
+        s.apply_fused(qubits, U)
+        ref = oracle_mod.apply_dense(ref, qubits, U)
+    check(s.download(), ref, dtype, f"n={n} k={k}")
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_fused_low_qubits(q, oracle_mod, dtype):
+    """Fused gates on the lowest qubits (partners inside one 64-byte run) and on mixed low/high sets."""
+    n = 14
+    rng = np.random.default_rng(17)
+    psi = wl.gaussian_state(n, 17)
+    s = gpu_state(q, psi, dtype)
+    ref = psi.copy()
+    for qubits in ([0, 1, 2, 3, 4], [4, 3, 2, 1, 0], [0, 13, 5, 2], [13, 12, 11, 10, 9], [1, 7, 3]):
+        k = len(qubits)
+        Z = rng.standard_normal((2 ** k, 2 ** k)) + 1j * rng.standard_normal((2 ** k, 2 ** k))
+        U, _ = np.linalg.qr(Z)
+        s.apply_fused(qubits, U)
+        ref = oracle_mod.apply_dense(ref, qubits, U)
+    check(s.download(), ref, dtype)
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("n", [1, 4, 9, 13, 20])
+def test_reductions(q, oracle_mod, dtype, n):
+    psi = wl.gaussian_state(n, 40 + n) * 0.75
+    if dtype == "c64":
+        psi = psi.astype(np.complex64).astype(np.complex128)
+    s = gpu_state(q, psi, dtype)
+    nrm = s.norm()
+    assert abs(nrm - oracle_mod.norm(psi)) <= 1e-14
+    p = s.probs()
+    assert np.max(np.abs(p - oracle_mod.probs(psi))) <= 1e-16
+    pd = s.probs(device=True).cpu().numpy()
+    assert np.array_equal(pd, p)
+    m = s.marginals()
+    assert np.max(np.abs(m - oracle_mod.marginals(psi))) <= 1e-14
+    before = s.renormalize()
+    assert abs(before - nrm) <= 1e-15 * max(1.0, nrm)
+    got = s.download().astype(np.complex128)
+    want = psi / math.sqrt(oracle_mod.norm(psi))
+    check(got, want, dtype)
+    assert abs(s.norm() - 1.0) <= (1e-14 if dtype == "c128" else 1e-6)
+
+
+def test_reduction_determinism(q):
+    n = 22
+    psi = wl.gaussian_state(n, 3)
+    s = gpu_state(q, psi, "c128")
+    vals = {s.norm() for _ in range(3)}
+    assert len(vals) == 1
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_sampling(q, dtype):
+    """Sampling of the final state (Sec. V): a basis state always yields its index; a two-outcome
+    state yields each index at the inverse-CDF cut."""
+    n = 15
+    s = q.State(n, dtype)
+    s.set_basis(12345)
+    assert list(s.sample([0.0, 0.5, 0.999999])) == [12345] * 3
+    psi = np.zeros(2 ** n, np.complex128)
+    psi[3] = math.sqrt(0.25)
+    psi[2 ** n - 2] = math.sqrt(0.75) * 1j
+    s.upload(psi)
+    out = s.sample([0.0, 0.1, 0.2499, 0.2501, 0.6, 0.99])
+    assert list(out) == [3, 3, 3, 2 ** n - 2, 2 ** n - 2, 2 ** n - 2]
+
+
+def run_gpu(q, text, dtype, method="plain", psi0=None, fuse_k=5, use_graph=False, reps=1):
+    c = q.parse_circuit(text)
+    s = q.State(c.n, dtype)
+    p = q.Plan(c, dtype, method=method, fuse_k=fuse_k, use_graph=use_graph)
+    outs = []
+    for _ in range(reps):
+        if psi0 is None:
+            s.set_basis(c.init)
+        else:
+            s.upload(psi0)
+        p.execute(s)
+        outs.append(s.download().astype(np.complex128))
+    return outs[-1] if reps == 1 else outs, p
+
+
+def compare_circuit(got, ref, dtype, what):
+    if dtype == "c128":
+        d = np.max(np.abs(got - ref))
+        assert d <= TOL128, f"{what}: max|d| = {d:.3e}"
+    else:
+        import oracle
+        f = oracle.infidelity(got, ref)
+        assert f <= TOL64_FID, f"{what}: 1-F = {f:.3e}"
+
+
+@pytest.mark.parametrize("method", ["plain", "fused"])
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_config0_random_circuit(q, oracle_mod, method, seed):
+    """16 qubits, complex128: H on every qubit then 200 random gates (start |0...0>)."""
+    text = wl.config0_circuit(16, 200, seed)
+    ref = oracle_mod.run_circuit(text)
+    got, p = run_gpu(q, text, "c128", method)
+    compare_circuit(got, ref, "c128", f"seed {seed} {method}")
+    assert abs(np.sum(np.abs(got) ** 2) - 1) < 1e-13
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("method,k", [("plain", 5), ("fused", 2), ("fused", 3), ("fused", 4), ("fused", 5)])
+def test_brickwork_small(q, oracle_mod, dtype, method, k):
+    text = wl.brickwork_circuit(14, 6, seed=21)
+    ref = oracle_mod.run_circuit(text)
+    got, p = run_gpu(q, text, dtype, method, fuse_k=k)
+    compare_circuit(got, ref, dtype, f"{method} k={k}")
+    if method == "fused":
+        assert p.info["launches"] < p.info["gates"]
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("method", ["plain", "fused"])
+@pytest.mark.parametrize("n", [6, 12, 18])
+def test_qft_gaussian_state(q, oracle_mod, dtype, method, n):
+    psi = wl.gaussian_state(n, 12)
+    text = wl.qft_circuit(n)
+    ref = oracle_mod.run_circuit(text, psi0=psi)
+    got, _ = run_gpu(q, text, dtype, method, psi0=psi)
+    compare_circuit(got, ref, dtype, f"qft n={n} {method}")
+
+
+@pytest.mark.parametrize("method", ["plain", "fused"])
+def test_ripple_adder_bit_exact_small(q, method):
+    m = 4
+    text, lay = wl.ripple_adder_circuit(m)
+    c = q.parse_circuit(text)
+    p = q.Plan(c, "c128", method=method)
+    s = q.State(lay["n"], "c128")
+    for a in range(2 ** m):
+        for b in range(0, 2 ** m, 3):
+            s.set_basis(a | (b << m))
+            p.execute(s)
+            got = s.download()
+            want = a | (((a + b) % 2 ** m) << m)
+            assert got[want] == 1.0 and np.count_nonzero(got) == 1, (a, b)
+
+
+def test_graph_replay_matches_eager(q, oracle_mod):
+    """A plan recorded in a HIP graph, replayed several times with eager work in between."""
+    import torch
+    text = wl.config0_circuit(12, 120, seed=5)
+    ref = oracle_mod.run_circuit(text)
+    c = q.parse_circuit(text)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        s = q.State(c.n, "c128")
+        p = q.Plan(c, "c128", method="fused", use_graph=True)
+        for rep in range(4):
+            s.set_basis(0)
+            p.execute(s)
+            got = s.download()
+            compare_circuit(got, ref, "c128", f"replay {rep}")
+            s.apply_1q(0, np.eye(2) * 1j)  # eager work between replays
+            s.sync()
