@@ -151,6 +151,8 @@ def main() -> int:
     ap.add_argument("--dtype", default="c128")
     ap.add_argument("--method", default="fused", choices=["fused", "staged", "plain"])
     ap.add_argument("--fuse-k", type=int, default=5)
+    ap.add_argument("--lds", type=int, default=0, help="resident qubits per LDS block (staged plans)")
+    ap.add_argument("--lds-regs", type=int, default=0, help="log2 amplitudes per thread (staged plans)")
     ap.add_argument("--plain-runs", type=int, default=1, help="timed runs of the plain per-gate plan (0 = skip)")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--cpu-n", type=int, default=26)
@@ -182,7 +184,7 @@ def main() -> int:
     G = len(circ.gates)
     log(f"{G} gates; allocating {amp * 2 ** n / 2 ** 30:.0f} GiB state")
     state = q.State(n, dtype, device=dev)
-    plan = q.Plan(circ, dtype, method=args.method, fuse_k=args.fuse_k)
+    plan = q.Plan(circ, dtype, method=args.method, fuse_k=args.fuse_k, lds_qubits=args.lds, lds_regs=args.lds_regs)
     log(f"plan {args.method}: {plan.info}")
 
     def step(timed: bool):

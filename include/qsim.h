@@ -197,6 +197,8 @@ typedef struct qsim_plan_opts {
     int32_t lds_qubits; /* QSIM_PLAN_STAGED: qubits resident per LDS block (0 = default) */
     int32_t use_graph;  /* nonzero: record the launch sequence in a HIP graph on the first execute
                            and replay it afterwards (per state) */
+    int32_t lds_regs;   /* QSIM_PLAN_STAGED: log2 of the amplitudes each thread holds in registers
+                           (0 = default; 3..5 allowed); the thread count is 2^(lds_qubits - lds_regs) */
 } qsim_plan_opts;
 
 typedef struct qsim_plan_info {

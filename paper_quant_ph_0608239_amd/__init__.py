@@ -180,11 +180,11 @@ class Plan:
     """A circuit lowered once to kernel launches (plain sweeps, fused k-qubit gates or LDS passes)."""
 
     def __init__(self, circuit: Circuit, dtype="c128", method="plain", fuse_k: int = 5, lds_qubits: int = 0,
-                 use_graph: bool = False):
+                 use_graph: bool = False, lds_regs: int = 0):
         self.n = circuit.n
         self.dtype = dtype_code(dtype)
         opts = _lib.PlanOpts(_METHODS[method] if isinstance(method, str) else int(method), int(fuse_k),
-                             int(lds_qubits), int(bool(use_graph)))
+                             int(lds_qubits), int(bool(use_graph)), int(lds_regs))
         arr = circuit.gate_array()
         h = ctypes.c_void_p()
         check(lib().qsim_plan_create(self.n, self.dtype, arr, len(circuit.gates), ctypes.byref(opts), ctypes.byref(h)))

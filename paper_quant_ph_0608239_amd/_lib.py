@@ -42,7 +42,7 @@ class Gate(ctypes.Structure):
 
 class PlanOpts(ctypes.Structure):
     _fields_ = [("method", ctypes.c_int32), ("fuse_k", ctypes.c_int32), ("lds_qubits", ctypes.c_int32),
-                ("use_graph", ctypes.c_int32)]
+                ("use_graph", ctypes.c_int32), ("lds_regs", ctypes.c_int32)]
 
 
 class PlanInfo(ctypes.Structure):

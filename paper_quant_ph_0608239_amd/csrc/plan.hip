@@ -26,7 +26,8 @@ int launch_fused_mfma(qsim_state *s, int k, const int *qubits, const void *dev_w
 int launch_fused_valu(qsim_state *s, int k, const int *qubits, const double *U);
 
 struct StagedPlan;  // staged.hip
-int staged_build(int n, int dtype, const std::vector<qsim_gate> &gates, int lds_qubits, StagedPlan **out, qsim_plan_info *info);
+int staged_build(int n, int dtype, const std::vector<qsim_gate> &gates, int lds_qubits, int lds_regs, StagedPlan **out,
+                 qsim_plan_info *info);
 int staged_execute(StagedPlan *p, qsim_state *s);
 int staged_execute_timed(StagedPlan *p, qsim_state *s, double *ms, int32_t *kind, int32_t *fk);
 void staged_free(StagedPlan *p);
@@ -340,7 +341,7 @@ int qsim_plan_create(int n, int dtype, const qsim_gate *gates, int64_t ngates, c
     } else if (o.method == QSIM_PLAN_FUSED) {
         rc = build_fused(p, gl, o.fuse_k);
     } else {
-        rc = staged_build(n, dtype, gl, o.lds_qubits, &p->staged, &p->info);
+        rc = staged_build(n, dtype, gl, o.lds_qubits, o.lds_regs, &p->staged, &p->info);
     }
     if (rc) {
         qsim_plan_free(p);

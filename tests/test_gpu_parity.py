@@ -327,3 +327,86 @@ def test_graph_replay_matches_eager(q, oracle_mod):
             compare_circuit(got, ref, "c128", f"replay {rep}")
             s.apply_1q(0, np.eye(2) * 1j)  # eager work between replays
             s.sync()
+
+
+# ----------------------------------------------------------------------------------------------
+# LDS-staged plans: several gates per read/write of the state
+# ----------------------------------------------------------------------------------------------
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("lds", [0, 10, 11])
+def test_staged_brickwork(q, oracle_mod, dtype, lds):
+    if dtype == "c64" and lds == 10:
+        pytest.skip("complex64 blocks hold at least 2^11 amplitudes")
+    text = wl.brickwork_circuit(15, 8, seed=23)
+    ref = oracle_mod.run_circuit(text)
+    c = q.parse_circuit(text)
+    s = q.State(c.n, dtype)
+    p = q.Plan(c, dtype, method="staged", lds_qubits=lds)
+    assert p.info["passes"] < len(c.gates) // 4
+    p.execute(s)
+    compare_circuit(s.download().astype(np.complex128), ref, dtype, f"staged lds={lds}")
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("seed", [1, 2])
+def test_staged_config0(q, oracle_mod, dtype, seed):
+    """Random gates from the nine-name set: controls and diagonal gates inside and outside the
+    resident set, Pauli Y (general), CNOT with non-resident targets."""
+    text = wl.config0_circuit(16, 200, seed)
+    ref = oracle_mod.run_circuit(text)
+    got, p = run_gpu(q, text, dtype, "staged")
+    compare_circuit(got, ref, dtype, f"staged seed {seed}")
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("n", [13, 17])
+def test_staged_qft_with_swaps(q, oracle_mod, dtype, n):
+    psi = wl.gaussian_state(n, 12)
+    text = wl.qft_circuit(n)
+    ref = oracle_mod.run_circuit(text, psi0=psi)
+    got, p = run_gpu(q, text, dtype, "staged", psi0=psi)
+    compare_circuit(got, ref, dtype, f"staged qft n={n}")
+    assert p.info["passes"] <= 8
+
+
+def test_staged_adder_bit_exact(q):
+    m = 7
+    text, lay = wl.ripple_adder_circuit(m)
+    c = q.parse_circuit(text)
+    p = q.Plan(c, "c128", method="staged", lds_qubits=10)
+    s = q.State(lay["n"], "c128")
+    for a, b in wl.adder_operands(m, 16, seed=11):
+        s.set_basis(a | (b << m))
+        p.execute(s)
+        got = s.download()
+        want = a | (((a + b) % 2 ** m) << m)
+        assert got[want] == 1.0 and np.count_nonzero(got) == 1, (a, b)
+
+
+def test_staged_controlled_everything(q, oracle_mod):
+    """Controlled general gates, Toffolis and controlled swaps with controls on every kind of bit."""
+    n = 14
+    rng = np.random.default_rng(99)
+    lines = []
+    for _ in range(120):
+        kind = rng.integers(0, 5)
+        qs = [int(x) for x in rng.permutation(n)[:3]]
+        if kind == 0:
+            lines.append(f"CV {qs[0]} {qs[1]} {float(rng.uniform(0, 6)).hex()}")
+        elif kind == 1:
+            lines.append(f"TOFFOLI {qs[0]} {qs[1]} {qs[2]}")
+        elif kind == 2:
+            lines.append(f"QSWAP {qs[0]} {qs[1]}")
+        elif kind == 3:
+            lines.append(wl.u_line(qs[0], wl.haar_2x2(rng)))
+        else:
+            lines.append(f"CRK {qs[0]} {qs[1]} {int(rng.integers(1, 9))}")
+    text = wl.circuit_text(n, lines)
+    psi = wl.gaussian_state(n, 5)
+    ref = oracle_mod.run_circuit(text, psi0=psi)
+    for lds in (10, 12):
+        c = q.parse_circuit(text)
+        s = q.State(n, "c128")
+        s.upload(psi)
+        q.Plan(c, "c128", method="staged", lds_qubits=lds).execute(s)
+        compare_circuit(s.download(), ref, "c128", f"lds={lds}")
