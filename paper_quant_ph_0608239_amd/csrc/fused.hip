@@ -39,14 +39,6 @@ __device__ __forceinline__ f4_t mfma16(float a, float b, f4_t c)
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
-__device__ __forceinline__ uint64_t insert_zeros(uint64_t j, const IndexMap &m)
-{
-    for (int s = 0; s < m.npos; ++s) {
-        const uint64_t lo = j & ((uint64_t(1) << m.pos[s]) - 1);
-        j = lo | ((j ^ lo) << 1);
-    }
-    return j | m.set;
-}
 
 struct QubitList {
     int32_t k;
@@ -107,6 +99,9 @@ __global__ __launch_bounds__(kBlock) void k_fused_mfma(T *__restrict__ a, uint64
         for (int kk = 0; kk < NA; ++kk) x[kk] = *reinterpret_cast<const C *>(a + 2 * (b + off[kk]));
     }
     while (tile < ntiles) {
+        // W stays in LDS and is re-read every tile (a compiler barrier keeps it from being hoisted
+        // into 2^(2k-4) registers per lane), which leaves room for more resident waves
+        asm volatile("" ::: "memory");
         const uint64_t b = insert_zeros(tile * 16 + col, map);
         const uint64_t next = tile + wstride;
         // prefetch the next tile of this wave before the contraction of the current one
@@ -116,16 +111,16 @@ __global__ __launch_bounds__(kBlock) void k_fused_mfma(T *__restrict__ a, uint64
 #pragma unroll
             for (int kk = 0; kk < NA; ++kk) xn[kk] = *reinterpret_cast<const C *>(a + 2 * (bn + off[kk]));
         }
+        // K-step outer, row block inner: the MB accumulator chains are independent, so
+        // consecutive matrix-core instructions never wait on each other's results
         AV acc[MB];
 #pragma unroll
-        for (int mb = 0; mb < MB; ++mb) {
-            acc[mb] = AV{0, 0, 0, 0};
+        for (int mb = 0; mb < MB; ++mb) acc[mb] = AV{0, 0, 0, 0};
 #pragma unroll
-            for (int kk = 0; kk < KS; ++kk) {
-                const T av = W[(mb * KS + kk) * 64 + lane];
-                const T bv = kk < NA ? x[kk].x : x[kk - NA].y;
-                acc[mb] = mfma16(av, bv, acc[mb]);
-            }
+        for (int kk = 0; kk < KS; ++kk) {
+            const T bv = kk < NA ? x[kk].x : x[kk - NA].y;
+#pragma unroll
+            for (int mb = 0; mb < MB; ++mb) acc[mb] = mfma16(W[(mb * KS + kk) * 64 + lane], bv, acc[mb]);
         }
 #pragma unroll
         for (int mb = 0; mb < MB / 2; ++mb)

@@ -55,14 +55,28 @@ __host__ __device__ inline uint64_t dim(int n) { return uint64_t(1) << n; }
 // enumerates j in [0, 2^(n-m)) and forms the base index by inserting a 0 bit at every p_s
 // (ascending), then OR-ing `set` (the control bits that must be 1).
 // ---------------------------------------------------------------------------------------------
-constexpr int kMaxPos = 48;
 struct IndexMap {
     uint64_t set;       // OR-ed into the base index
-    int32_t npos;       // number of inserted zero bits
-    uint8_t pos[kMaxPos];  // sorted ascending
+    uint64_t posmask;   // positions of the inserted zero bits
+    int32_t npos;       // number of inserted zero bits (popcount of posmask)
+    int32_t p0;         // lowest inserted position (64 if none)
 };
 
 IndexMap make_index_map(uint64_t posmask, uint64_t set);
+
+// Insert a zero bit at every position of m.posmask (ascending) into j, then OR m.set. The positions
+// are walked with count-trailing-zeros on the (wave-uniform) mask: no memory access in the loop.
+__device__ __forceinline__ uint64_t insert_zeros(uint64_t j, const IndexMap &m)
+{
+    uint64_t pm = m.posmask;
+    while (pm) {
+        const int p = __builtin_ctzll(pm);
+        pm &= pm - 1;
+        const uint64_t lo = j & ((uint64_t(1) << p) - 1);
+        j = lo | ((j ^ lo) << 1);
+    }
+    return j | m.set;
+}
 
 // 2x2 complex matrix in kernel arguments (FP64 always; c64 kernels round at use)
 struct Mat2 {

@@ -49,14 +49,6 @@ template <bool NT, typename W> __device__ __forceinline__ void stw(void *p, cons
     else *reinterpret_cast<V *>(p) = v;
 }
 
-__device__ __forceinline__ uint64_t insert_zeros(uint64_t j, const IndexMap &m)
-{
-    for (int s = 0; s < m.npos; ++s) {
-        const uint64_t lo = j & ((uint64_t(1) << m.pos[s]) - 1);
-        j = lo | ((j ^ lo) << 1);
-    }
-    return j | m.set;
-}
 
 template <typename T> struct CMat {
     T r[4], i[4];
@@ -357,14 +349,14 @@ inline unsigned grid_for(uint64_t items, uint64_t per_block)
 
 // VEC = 2 (two neighbouring amplitudes per lane) is legal when bit 0 is not an inserted position
 // and there is an even number of items
-inline bool can_vec2(const IndexMap &m, uint64_t items) { return (m.npos == 0 || m.pos[0] > 0) && (items % 2 == 0); }
+inline bool can_vec2(const IndexMap &m, uint64_t items) { return m.p0 > 0 && (items % 2 == 0); }
 
 constexpr int kItems = 4;
 
 // contiguous run (bytes) that every lane's word belongs to: set by the lowest inserted position
 template <typename T> inline bool streaming(const IndexMap &m)
 {
-    const int p0 = m.npos ? m.pos[0] : 63;
+    const int p0 = m.p0 > 63 ? 63 : m.p0;
     return (uint64_t(2 * sizeof(T)) << (p0 > 40 ? 40 : p0)) >= 256;
 }
 
@@ -485,9 +477,9 @@ IndexMap make_index_map(uint64_t posmask, uint64_t set)
 {
     IndexMap m{};
     m.set = set;
-    m.npos = 0;
-    for (int q = 0; q < 64; ++q)
-        if ((posmask >> q) & 1) m.pos[m.npos++] = uint8_t(q);
+    m.posmask = posmask;
+    m.npos = __builtin_popcountll(posmask);
+    m.p0 = posmask ? __builtin_ctzll(posmask) : 64;
     return m;
 }
 
