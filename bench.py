@@ -138,9 +138,35 @@ def sweep_mode(args) -> int:
     return 0
 
 
+def batch_mode(args) -> int:
+    """Many independent circuits in one persistent launch: circuits/s, gates/s and per-circuit
+    latency percentiles from device timestamps. One JSON line."""
+    import numpy as np
+    import torch
+
+    import paper_quant_ph_0608239_amd as q
+    import qsim_workloads as wl
+    texts = wl.batch_circuits(count=args.count, nmin=10, nmax=22, depth=50, seed=41)
+    b = q.Batch(texts, args.dtype, lds_qubits=args.lds, lds_regs=args.lds_regs, use_graph=False)
+    for _ in range(args.warmup):
+        b.run()
+    runs = [b.run() for _ in range(args.steps)]
+    ms = float(np.mean([r["launch_ms"] for r in runs]))
+    lat = b.latencies_us()
+    out = {"metric": "circuits/s (batch of independent circuits, one persistent launch)", "value": round(args.count / ms * 1e3, 1),
+           "unit": "circuits/s", "gates_per_s": round(b.total_gates / ms * 1e3, 1), "ms_per_launch": round(ms, 3),
+           "latency_us": {"p50": round(float(np.percentile(lat, 50)), 1), "p99": round(float(np.percentile(lat, 99)), 1),
+                          "max": round(float(lat.max()), 1)},
+           "config": {"workload": f"batch-{args.count}-circuits-n10-22-depth50-{args.dtype}", "count": args.count,
+                      "gates": b.total_gates, "seed": 41}, "dtype": "f64" if args.dtype == "c128" else "f32"}
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
-    ap.add_argument("--mode", default="bench", choices=["bench", "sweep"])
+    ap.add_argument("--mode", default="bench", choices=["bench", "sweep", "batch"])
+    ap.add_argument("--count", type=int, default=2048)
     ap.add_argument("--targets", default="all")
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
@@ -160,6 +186,8 @@ def main() -> int:
     args = ap.parse_args()
     if args.mode == "sweep":
         return sweep_mode(args)
+    if args.mode == "batch":
+        return batch_mode(args)
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (no sharding, no "

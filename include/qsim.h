@@ -251,15 +251,17 @@ typedef struct qsim_batch_stats {
     int64_t gates;
 } qsim_batch_stats;
 
-/* Build a batch of `count` circuits for one dtype: circuit c has nqubits[c] qubits (1..24) and the
- * gates gates[offsets[c] .. offsets[c+1]-1]; every circuit starts from |0...0>. The gate tables
- * and the state pool are placed in device memory (owned by the batch).
- * EINVAL on malformed input, ENOMEM if the pool does not fit. */
+/* Build a batch of `count` circuits for one dtype: circuit c has nqubits[c] qubits (1..26) and the
+ * gates gates[offsets[c] .. offsets[c+1]-1] (offsets has count + 1 entries, offsets[0] = 0); every
+ * circuit starts from |0...0>. Each circuit is scheduled into LDS-staged passes (opts: lds_qubits,
+ * lds_regs as for QSIM_PLAN_STAGED; use_graph records the launch in a HIP graph on the first run,
+ * which needs a non-NULL stream; opts may be NULL). The gate tables and the state pool are placed in
+ * device memory owned by the batch. EINVAL on malformed input, ENOMEM if the pool does not fit. */
 int qsim_batch_create(int count, const int *nqubits, const int64_t *offsets, const qsim_gate *gates, int dtype,
-                      void *stream, qsim_batch **out);
-/* Run every circuit of the batch from |0...0> in one persistent kernel launch. stats may be NULL.
- * Per-circuit device timestamps (claim -> finish, in device clock ticks) are kept for
- * qsim_batch_latencies. Synchronises. */
+                      const qsim_plan_opts *opts, void *stream, qsim_batch **out);
+/* Run every circuit of the batch from |0...0> in one persistent kernel launch (workgroups walk the
+ * circuits largest first in a fixed cyclic order). stats may be NULL. Per-circuit device timestamps
+ * (start -> finish) are kept for qsim_batch_latencies. Synchronises. */
 int qsim_batch_run(qsim_batch *b, qsim_batch_stats *stats);
 /* Per-circuit latencies of the last run in microseconds (host array of count doubles). */
 int qsim_batch_latencies(qsim_batch *b, double *out_us);

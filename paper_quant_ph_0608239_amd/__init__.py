@@ -224,7 +224,8 @@ class Plan:
 class Batch:
     """Many independent small circuits run from |0...0> in one persistent launch."""
 
-    def __init__(self, circuits: list, dtype="c64", device="cuda:0"):
+    def __init__(self, circuits: list, dtype="c64", device="cuda:0", lds_qubits: int = 0, lds_regs: int = 0,
+                 use_graph: bool = False):
         import torch
         cs = [parse_circuit(c) if isinstance(c, str) else c for c in circuits]
         self.count = len(cs)
@@ -235,14 +236,15 @@ class Batch:
         for c in cs:
             gates.extend(c.gates)
             offs.append(len(gates))
-        self.total_gates = len(gates)
+        self.total_gates = len(gates)  # gates over all circuits
         garr = (Gate * max(1, len(gates)))(*gates)
         nq = (ctypes.c_int * self.count)(*self.nqubits)
         of = (ctypes.c_int64 * (self.count + 1))(*offs)
         h = ctypes.c_void_p()
+        opts = _lib.PlanOpts(PLAN_STAGED, 0, int(lds_qubits), int(bool(use_graph)), int(lds_regs))
         with torch.cuda.device(torch.device(device)):
-            check(lib().qsim_batch_create(self.count, nq, of, garr, self.dtype, _stream_ptr(torch.device(device)),
-                                          ctypes.byref(h)))
+            check(lib().qsim_batch_create(self.count, nq, of, garr, self.dtype, ctypes.byref(opts),
+                                          _stream_ptr(torch.device(device)), ctypes.byref(h)))
         self.handle = h
 
     def run(self) -> dict:

@@ -410,3 +410,47 @@ def test_staged_controlled_everything(q, oracle_mod):
         s.upload(psi)
         q.Plan(c, "c128", method="staged", lds_qubits=lds).execute(s)
         compare_circuit(s.download(), ref, "c128", f"lds={lds}")
+
+
+# ----------------------------------------------------------------------------------------------
+# Batches of independent circuits in one persistent launch
+# ----------------------------------------------------------------------------------------------
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_batch_against_oracle(q, oracle_mod, dtype):
+    texts = wl.batch_circuits(count=24, nmin=3, nmax=15, depth=50, seed=41)
+    texts.append(wl.circuit_text(5, []))                       # no gates at all
+    texts.append(wl.config0_circuit(13, 80, seed=9))            # H prefix, above one block
+    b = q.Batch(texts, dtype)
+    st = b.run()
+    assert st["circuits"] == len(texts)
+    for rep in range(2):  # the second run starts again from |0...0>
+        if rep:
+            b.run()
+        for c, text in enumerate(texts):
+            ref = oracle_mod.run_circuit(text)
+            got = b.download(c).astype(np.complex128)
+            compare_circuit(got, ref, dtype, f"circuit {c} rep {rep}")
+    lat = b.latencies_us()
+    assert np.all(lat > 0) and np.all(np.isfinite(lat))
+
+
+def test_batch_graph_replay(q, oracle_mod):
+    import torch
+    texts = wl.batch_circuits(count=16, nmin=10, nmax=14, depth=30, seed=5)
+    refs = [oracle_mod.run_circuit(t) for t in texts]
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        b = q.Batch(texts, "c128", use_graph=True)
+        for rep in range(3):
+            b.run()
+            for c in range(len(texts)):
+                compare_circuit(b.download(c), refs[c], "c128", f"replay {rep} circuit {c}")
+
+
+@pytest.mark.parametrize("variant", [(11, 3), (11, 4)])
+def test_batch_variants(q, oracle_mod, variant):
+    texts = wl.batch_circuits(count=10, nmin=9, nmax=13, depth=40, seed=77)
+    b = q.Batch(texts, "c128", lds_qubits=variant[0], lds_regs=variant[1])
+    b.run()
+    for c, t in enumerate(texts):
+        compare_circuit(b.download(c), oracle_mod.run_circuit(t), "c128", f"{variant} circuit {c}")
