@@ -175,7 +175,8 @@ def main() -> int:
     ap.add_argument("--layers", type=int, default=20)
     ap.add_argument("--seed", type=int, default=21)
     ap.add_argument("--dtype", default="c128")
-    ap.add_argument("--method", default="fused", choices=["fused", "staged", "plain"])
+    ap.add_argument("--method", default="auto", choices=["auto", "fused", "staged", "plain"],
+                    help="auto: the autotuner times the candidate plans on the state (outside the timed region)")
     ap.add_argument("--fuse-k", type=int, default=5)
     ap.add_argument("--lds", type=int, default=0, help="resident qubits per LDS block (staged plans)")
     ap.add_argument("--lds-regs", type=int, default=0, help="log2 amplitudes per thread (staged plans)")
@@ -212,7 +213,19 @@ def main() -> int:
     G = len(circ.gates)
     log(f"{G} gates; allocating {amp * 2 ** n / 2 ** 30:.0f} GiB state")
     state = q.State(n, dtype, device=dev)
-    plan = q.Plan(circ, dtype, method=args.method, fuse_k=args.fuse_k, lds_qubits=args.lds, lds_regs=args.lds_regs)
+    tuned = None
+    if args.method == "auto":
+        from paper_quant_ph_0608239_amd import tuning
+        t0 = time.perf_counter()
+        tuned = tuning.tune(circ, state, reps=1, include_plain=False, use_cache=False)
+        log(f"autotune ({time.perf_counter() - t0:.1f} s): best {tuned['method']} k={tuned['fuse_k']} "
+            f"lds={tuned['lds_qubits']}/{tuned['lds_regs']} {tuned['ms']:.1f} ms; tried "
+            + ", ".join(f"{t['method']}:{t['fuse_k'] or ''}{t['lds_qubits'] or ''}/{t['lds_regs'] or ''}={t['ms']:.0f}"
+                        for t in tuned["tried"]))
+        plan = q.Plan(circ, dtype, method=tuned["method"], fuse_k=tuned["fuse_k"] or 5, lds_qubits=tuned["lds_qubits"],
+                      lds_regs=tuned["lds_regs"])
+    else:
+        plan = q.Plan(circ, dtype, method=args.method, fuse_k=args.fuse_k, lds_qubits=args.lds, lds_regs=args.lds_regs)
     log(f"plan {args.method}: {plan.info}")
 
     def step(timed: bool):
@@ -276,8 +289,14 @@ def main() -> int:
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64" if dtype == "c128" else "f32", "data": "synthetic",
         "config": {"workload": workload, "n_qubits": n, "state": dtype, "layers": args.layers, "gates": G,
-                   "seed": args.seed, "method": args.method, "fuse_k": args.fuse_k if args.method == "fused" else None,
-                   "launches_per_step": int(plan.info["launches"])},
+                   "seed": args.seed, "method": ["plain", "fused", "staged"][int(plan.info["method"])],
+                   "fuse_k": int(plan.info["fuse_k"]) or None, "lds_qubits": int(plan.info["lds_qubits"]) or None,
+                   "launches_per_step": int(plan.info["launches"]),
+                   "autotune": None if tuned is None else {
+                       "choice": {k: tuned[k] for k in ("method", "fuse_k", "lds_qubits", "lds_regs")},
+                       "tried_ms": {f"{t['method']}{'-k' + str(t['fuse_k']) if t['method'] == 'fused' else ''}"
+                                    f"{'-m' + str(t['lds_qubits']) + 'r' + str(t['lds_regs']) if t['method'] == 'staged' else ''}":
+                                    round(t["ms"], 1) for t in tuned["tried"]}}},
         "eff_GBps": round(eff_gbps, 1), "hbm_frac": round(eff_gbps / HBM_PEAK_GBPS, 4),
         "roofline": roof,
     }

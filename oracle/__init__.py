@@ -273,3 +273,17 @@ def infidelity(psi: np.ndarray, ref: np.ndarray) -> float:
     nr = np.sum(ref.real ** 2 + ref.imag ** 2)
     nps = np.sum(psi.real ** 2 + psi.imag ** 2)
     return float(1.0 - (ov.real ** 2 + ov.imag ** 2) / (nr * nps))
+
+
+def qft_sample(psi: np.ndarray, ks) -> np.ndarray:
+    """Selected outputs of the quantum Fourier transform of psi (the Fourier representation used in
+    the paper's Shor analysis, Sec. V): out_k = 2^{-n/2} sum_x psi_x e^{+2 pi i x k / 2^n}, with the
+    phase x k reduced modulo 2^n exactly in integer arithmetic; one O(2^n) sum per k."""
+    psi = np.asarray(psi, np.complex128)
+    N = psi.size
+    x = np.arange(N, dtype=np.int64)
+    out = []
+    for k in ks:
+        ph = (x * int(k)) % N
+        out.append(np.sum(psi * np.exp(2j * np.pi * ph / N)) / math.sqrt(N))
+    return np.array(out)

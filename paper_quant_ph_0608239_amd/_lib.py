@@ -92,6 +92,8 @@ SIGNATURES = {
     "qsim_plan_execute": (_i32, [_vp, _vp]),
     "qsim_plan_free": (_i32, [_vp]),
     "qsim_plan_execute_timed": (_i32, [_vp, _vp, _dp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]),
+    "qsim_plan_tune": (_i32, [_i32, _i32, ctypes.POINTER(Gate), _i64, _vp, _i32, _i32, ctypes.POINTER(PlanOpts), _dp,
+                              ctypes.POINTER(PlanOpts), _dp, _i32, ctypes.POINTER(_i32)]),
     "qsim_batch_create": (_i32, [_i32, ctypes.POINTER(_i32), ctypes.POINTER(_i64), ctypes.POINTER(Gate), _i32,
                                  ctypes.POINTER(PlanOpts), _vp, ctypes.POINTER(_vp)]),
     "qsim_batch_run": (_i32, [_vp, ctypes.POINTER(BatchStats)]),

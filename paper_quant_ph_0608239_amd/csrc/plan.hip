@@ -322,7 +322,9 @@ int qsim_plan_create(int n, int dtype, const qsim_gate *gates, int64_t ngates, c
     std::vector<qsim_gate> gl(gates, gates + ngates);
     for (const qsim_gate &g : gl)
         if (int rc = validate_gate(g, n)) return rc;
-    if (o.method == QSIM_PLAN_AUTO) o.method = QSIM_PLAN_FUSED;  // replaced by the tuner's choice below
+    // without a tuned choice: LDS-staged passes when the state holds at least one block of 2^12
+    // amplitudes (the fastest form measured on the brickwork and QFT families), else fusion
+    if (o.method == QSIM_PLAN_AUTO) o.method = n >= 12 ? QSIM_PLAN_STAGED : QSIM_PLAN_FUSED;
     qsim_plan *p = new qsim_plan();
     p->id = g_plan_ids.fetch_add(1);
     p->n = n;
@@ -408,6 +410,58 @@ int qsim_plan_execute_timed(qsim_plan *p, qsim_state *s, double *launch_ms, int3
     if (!p || !s || !s->data) return set_error(QSIM_EINVAL, "null argument");
     if (p->n != s->n || p->dtype != s->dtype) return set_error(QSIM_EINVAL, "plan and state differ in n or dtype");
     return run_steps_timed(p, s, launch_ms, kind, fused_k);
+}
+
+int qsim_plan_tune(int n, int dtype, const qsim_gate *gates, int64_t ngates, qsim_state *scratch, int reps,
+                   int include_plain, qsim_plan_opts *best, double *best_ms, qsim_plan_opts *tried_opts, double *tried_ms,
+                   int max_tried, int *ntried)
+{
+    if (!scratch || !scratch->data || !best || !best_ms) return set_error(QSIM_EINVAL, "null argument");
+    if (scratch->n != n || scratch->dtype != dtype) return set_error(QSIM_EINVAL, "tune: scratch state differs in n or dtype");
+    if (reps < 1) reps = 1;
+    std::vector<qsim_plan_opts> cand;
+    if (include_plain) cand.push_back(qsim_plan_opts{QSIM_PLAN_PLAIN, 0, 0, 0, 0});
+    for (int k = 2; k <= 5; ++k) cand.push_back(qsim_plan_opts{QSIM_PLAN_FUSED, k, 0, 0, 0});
+    const int variants[][2] = {{12, 4}, {11, 4}, {11, 3}, {10, 3}, {13, 4}};
+    for (auto &v : variants) cand.push_back(qsim_plan_opts{QSIM_PLAN_STAGED, 0, v[0], 0, v[1]});
+    hipEvent_t e0, e1;
+    QSIM_HIP(hipEventCreate(&e0));
+    QSIM_HIP(hipEventCreate(&e1));
+    double best_t = 1e300;
+    int nt = 0;
+    for (const qsim_plan_opts &o : cand) {
+        qsim_plan *p = nullptr;
+        double ms = -1.0;
+        if (qsim_plan_create(n, dtype, gates, ngates, &o, &p) == QSIM_OK) {
+            int rc = qsim_plan_execute(p, scratch);  // warm-up (also loads the kernels)
+            if (rc == QSIM_OK) rc = qsim_sync(scratch);
+            if (rc == QSIM_OK) {
+                QSIM_HIP(hipEventRecord(e0, scratch->stream));
+                for (int r = 0; r < reps && rc == QSIM_OK; ++r) rc = qsim_plan_execute(p, scratch);
+                QSIM_HIP(hipEventRecord(e1, scratch->stream));
+                QSIM_HIP(hipEventSynchronize(e1));
+                float t = 0.f;
+                QSIM_HIP(hipEventElapsedTime(&t, e0, e1));
+                if (rc == QSIM_OK) ms = double(t) / reps;
+            }
+            qsim_plan_free(p);
+        }
+        if (tried_opts && tried_ms && nt < max_tried) {
+            tried_opts[nt] = o;
+            tried_ms[nt] = ms;
+        }
+        ++nt;
+        if (ms >= 0.0 && ms < best_t) {
+            best_t = ms;
+            *best = o;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (ntried) *ntried = nt;
+    if (best_t >= 1e300) return set_error(QSIM_EUNSUPPORTED, "tune: no candidate could run");
+    *best_ms = best_t;
+    return QSIM_OK;
 }
 
 int qsim_plan_free(qsim_plan *p)

@@ -33,7 +33,7 @@ __all__ = [
     "CONFIG0_KINDS", "random_gate_circuit", "config0_circuit", "brickwork_circuit",
     "qft_lines", "iqft_lines", "qft_circuit", "ripple_adder_circuit", "adder_operands",
     "qft_adder_circuit", "gaussian_state", "random_state", "batch_circuits", "hexf",
-    "circuit_text", "count_gates", "shor_circuit_layout",
+    "circuit_text", "count_gates", "shor_circuit_layout", "inverse_lines", "haar_2x2", "u_line",
 ]
 
 
@@ -130,17 +130,45 @@ def u_line(q: int, u: np.ndarray) -> str:
     return f"U {q} " + " ".join(vals)
 
 
-def brickwork_circuit(n: int, layers: int = 20, seed: int = 21) -> str:
+def brickwork_circuit(n: int, layers: int = 20, seed: int = 21, layer_range: tuple[int, int] | None = None) -> str:
     """Layer l = 0..layers-1: a Haar U on every qubit (qubit order 0..n-1), then CZ(q, q+1) for every
-    q = l (mod 2) with q+1 < n. Start |0...0>."""
+    q = l (mod 2) with q+1 < n. Start |0...0>. layer_range=(a, b) emits only layers a..b-1 (the random
+    draws of all layers are made in the same order, so the pieces concatenate to the full circuit)."""
     rng = np.random.default_rng(seed)
+    a, b = layer_range if layer_range else (0, layers)
     lines = []
     for layer in range(layers):
+        us = [haar_2x2(rng) for _ in range(n)]
+        if not a <= layer < b:
+            continue
         for q in range(n):
-            lines.append(u_line(q, haar_2x2(rng)))
+            lines.append(u_line(q, us[q]))
         for q in range(layer % 2, n - 1, 2):
             lines.append(f"CZ {q} {q + 1}")
-    return circuit_text(n, lines, header=[f"brickwork n={n} layers={layers} seed={seed}"])
+    return circuit_text(n, lines, header=[f"brickwork n={n} layers={layers} seed={seed} range={a}..{b - 1}"])
+
+
+def inverse_lines(text: str) -> list[str]:
+    """Gate lines of the exact inverse circuit: reversed order, every gate replaced by its inverse
+    (explicit U by its conjugate transpose, self-inverse gates unchanged). For the families used
+    here: U, CZ, H, X, Z, CNOT, TOFFOLI, QSWAP, CRK/CRKDG."""
+    out = []
+    for ln in reversed(text.splitlines()):
+        t = ln.split()
+        if not t or t[0] in ("QUBITS", "INITIAL", "!", "#") or t[0].startswith(("!", "#")):
+            continue
+        kw = t[0]
+        if kw == "U":
+            v = [float.fromhex(x) for x in t[2:10]]
+            u = np.array([[complex(v[0], v[1]), complex(v[2], v[3])], [complex(v[4], v[5]), complex(v[6], v[7])]])
+            out.append(u_line(int(t[1]), u.conj().T))
+        elif kw in ("CZ", "H", "X", "Z", "CNOT", "TOFFOLI", "QSWAP"):
+            out.append(ln)
+        elif kw in ("CRK", "CRKDG"):
+            out.append(("CRKDG " if kw == "CRK" else "CRK ") + " ".join(t[1:]))
+        else:
+            raise ValueError(f"no inverse rule for {kw}")
+    return out
 
 
 # --------------------------------------------------------------------------------------------
