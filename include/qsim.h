@@ -222,13 +222,16 @@ int qsim_plan_get_info(const qsim_plan *p, qsim_plan_info *info);
 int qsim_plan_execute(qsim_plan *p, qsim_state *s);
 int qsim_plan_free(qsim_plan *p);
 
-/* Autotuner: lower the circuit with every candidate method and parameter set (plain; fused with
- * k = 2..5; staged with the available resident-qubit / per-thread-register variants), execute each
- * `reps` times on `scratch` (a state of the same n and dtype whose contents are overwritten), and
- * return the options of the fastest in *best and its mean time per execute in *best_ms. The per-
- * candidate results (opts, ms; ms < 0 if the candidate is not available) are written to
- * tried_opts / tried_ms (arrays of max_tried entries, may be NULL); *ntried receives their number.
- * Timing uses HIP events on the scratch state's stream. EINVAL on bad arguments. */
+/* Autotuner: lower the circuit with every candidate method and parameter set (plain if
+ * include_plain; fused with k = 2..5; staged with the compiled resident-qubit / per-thread-register
+ * variants of the dtype), execute each `reps` times on `scratch` (a state of the same n and dtype
+ * whose contents are overwritten), and return the options of the fastest in *best and its mean
+ * time per execute in *best_ms. Candidates are timed in increasing order of their HBM lower bound
+ * (algorithmic bytes at 8 TB/s); one whose bound is not below the best time so far is not run. The
+ * per-candidate results (opts, ms; ms < 0 if the candidate is not available or was not run) are
+ * written to tried_opts / tried_ms (arrays of max_tried entries, may be NULL); *ntried receives
+ * the number of candidates. Timing uses HIP events on the scratch state's stream. EINVAL on bad
+ * arguments; EUNSUPPORTED if no candidate could run. */
 int qsim_plan_tune(int n, int dtype, const qsim_gate *gates, int64_t ngates, qsim_state *scratch, int reps,
                    int include_plain, qsim_plan_opts *best, double *best_ms, qsim_plan_opts *tried_opts, double *tried_ms,
                    int max_tried, int *ntried);
