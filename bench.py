@@ -163,9 +163,27 @@ def batch_mode(args) -> int:
     return 0
 
 
+def copycal_mode(args) -> int:
+    """Calibration of the HBM byte counters: a fill (writes only) and a device-to-device copy (reads
+    and writes) of a buffer of known size, so that FETCH_SIZE / WRITE_SIZE per dispatch can be
+    scaled to bytes."""
+    import torch
+    nbytes = int(args.copy_gib * 2 ** 30)
+    src = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda:0")
+    dst = torch.empty_like(src)
+    src.fill_(1.0)
+    for _ in range(args.steps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"mode": "copycal", "fill_bytes_written": nbytes, "copy_bytes_read": nbytes,
+                      "copy_bytes_written": nbytes, "copies": args.steps}), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
-    ap.add_argument("--mode", default="bench", choices=["bench", "sweep", "batch"])
+    ap.add_argument("--mode", default="bench", choices=["bench", "sweep", "batch", "copycal"])
+    ap.add_argument("--copy-gib", type=float, default=4.0, help="buffer size of --mode copycal")
     ap.add_argument("--count", type=int, default=2048)
     ap.add_argument("--targets", default="all")
     ap.add_argument("--gpus", type=int, default=1)
@@ -189,6 +207,8 @@ def main() -> int:
         return sweep_mode(args)
     if args.mode == "batch":
         return batch_mode(args)
+    if args.mode == "copycal":
+        return copycal_mode(args)
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (no sharding, no "
@@ -264,6 +284,8 @@ def main() -> int:
     dom_idx = classes[dom_key]
     dom_avg_ms = float(avg_per_launch[dom_idx].mean())
     dom_name = KERNEL_NAMES[dom_key[0]] + (f"_k{dom_key[1]}" if dom_key[1] else "")
+    if KERNEL_NAMES[dom_key[0]] == "staged":
+        dom_name += f"_m{plan.info['lds_qubits']}r{plan.info['lds_regs']}"
     full_sweep_bytes = 2.0 * amp * 2 ** n
     if dom_key[0] in (4, 5, 6):
         dom_bytes = full_sweep_bytes

@@ -210,7 +210,7 @@ typedef struct qsim_plan_info {
     int32_t method;         /* method actually used */
     int32_t fuse_k;         /* fused width used (QSIM_PLAN_FUSED) */
     int32_t lds_qubits;     /* resident qubits used (QSIM_PLAN_STAGED) */
-    int32_t reserved;
+    int32_t lds_regs;       /* log2 amplitudes per thread used (QSIM_PLAN_STAGED) */
 } qsim_plan_info;
 
 /* Lower `ngates` gates for states of n qubits and the given dtype. The gate list is copied.

@@ -191,7 +191,7 @@ class Plan:
         self.handle = h
         info = _lib.PlanInfo()
         check(lib().qsim_plan_get_info(h, ctypes.byref(info)))
-        self.info = {f: getattr(info, f) for f, _ in _lib.PlanInfo._fields_ if f != "reserved"}
+        self.info = {f: getattr(info, f) for f, _ in _lib.PlanInfo._fields_}
 
     def execute(self, state: State):
         check(lib().qsim_plan_execute(self.handle, state.handle))

@@ -48,7 +48,7 @@ class PlanOpts(ctypes.Structure):
 class PlanInfo(ctypes.Structure):
     _fields_ = [("gates", ctypes.c_int64), ("launches", ctypes.c_int64), ("passes", ctypes.c_int64),
                 ("alg_bytes", ctypes.c_double), ("alg_flops", ctypes.c_double), ("method", ctypes.c_int32),
-                ("fuse_k", ctypes.c_int32), ("lds_qubits", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("fuse_k", ctypes.c_int32), ("lds_qubits", ctypes.c_int32), ("lds_regs", ctypes.c_int32)]
 
 
 class BatchStats(ctypes.Structure):

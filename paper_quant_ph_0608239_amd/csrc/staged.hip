@@ -374,6 +374,7 @@ int staged_build(int n, int dtype, const std::vector<qsim_gate> &gates, int lds_
     }
     info->method = QSIM_PLAN_STAGED;
     info->lds_qubits = m;
+    info->lds_regs = log_e;
     info->launches = int64_t(passes.size());
     info->passes = int64_t(passes.size());
     info->alg_bytes = double(passes.size()) * 2.0 * std::ldexp(1.0, n) * amp_bytes(dtype);
