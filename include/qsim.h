@@ -123,6 +123,17 @@ int qsim_apply_swap(qsim_state *s, uint64_t control_mask, int q0, int q1);
  * EINVAL: k out of range, qubit out of range or repeated, NULL pointers. */
 int qsim_apply_fused(qsim_state *s, int k, const int *qubits, const double *U);
 
+/* The conditional operation of Shor's period finding (Sec. V, the step from Eq. Shor1 to Eq. Shor2):
+ * with x = the value of qubits x_first .. x_first+x_qubits-1 and z = the value of qubits
+ * f_first .. f_first+f_qubits-1 of a basis state, |x>|z> -> |x>|z XOR (y^x mod G)>. On a state whose
+ * f-register is |0> this writes f(x) = y^x mod G into it. The map is a permutation of basis states
+ * (its own inverse); amplitudes are moved without arithmetic, so the result is bit-exact. A table of
+ * the 2^x_qubits powers (4 bytes each) is allocated on the device for the call; the call returns
+ * after the permutation has finished on the state's stream.
+ * EINVAL: registers overlap or leave the state, x_qubits outside 1..30, f_qubits outside 1..32,
+ * G < 2, G > 2^f_qubits or G >= 2^32. ENOMEM / EDEVICE from the table allocation or the launch. */
+int qsim_apply_modexp(qsim_state *s, int x_first, int x_qubits, int f_first, int f_qubits, uint64_t y, uint64_t G);
+
 /* ---------------------------------------------------------------------------------------------
  * Reductions and normalisation (Eq. STAT1; probabilities Sec. II.A; <Q_i> Eq. Shor7)
  * All accumulate in FP64 for both dtypes.
@@ -206,7 +217,10 @@ typedef struct qsim_plan_info {
     int64_t launches;       /* kernel launches per execute */
     int64_t passes;         /* launches that read and write the whole state */
     double alg_bytes;       /* algorithmic HBM bytes per execute (per state) */
-    double alg_flops;       /* algorithmic flops of the fused contractions per execute */
+    double alg_flops;       /* algorithmic flops per execute: 8 * 2^(n+k) per fused k-qubit block;
+                               for gates applied one by one (plain and staged plans, unfused gates
+                               of fused plans) 14 flops per touched amplitude for a dense 2x2, 6 for
+                               a phase factor, 0 for permutations and exact sign changes */
     int32_t method;         /* method actually used */
     int32_t fuse_k;         /* fused width used (QSIM_PLAN_FUSED) */
     int32_t lds_qubits;     /* resident qubits used (QSIM_PLAN_STAGED) */

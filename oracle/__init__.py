@@ -70,6 +70,7 @@ def lib():
             "or_norm": [dp, i32],
             "or_marginals": [dp, i32, dp],
             "or_threads": [],
+            "or_modexp": [dp, i32, i32, i32, i32, i32, u64, u64],
         }
         for name, args in sigs.items():
             f = getattr(L, name)
@@ -183,6 +184,11 @@ def apply_op(a: np.ndarray, n: int, kw: str, args: list[str]) -> None:
         L.or_cv(p, n, 1 << iv(0), iv(1), fv(2))
     elif kw == "QSWAP":
         L.or_swap(p, n, iv(0), iv(1))
+    elif kw == "MODEXP":
+        xf, xq, ff, fq, y, G = (iv(k) for k in range(6))
+        if not (G >= 2 and G <= 2 ** fq and xf + xq <= n and ff + fq <= n and (xf + xq <= ff or ff + fq <= xf)):
+            raise ValueError("MODEXP: registers must be disjoint, inside the state, and G <= 2^fq")
+        L.or_modexp(p, n, xf, xq, ff, fq, y, G)
     else:
         raise ValueError(f"unknown gate keyword {kw!r}")
 
@@ -287,3 +293,53 @@ def qft_sample(psi: np.ndarray, ks) -> np.ndarray:
         ph = (x * int(k)) % N
         out.append(np.sum(psi * np.exp(2j * np.pi * ph / N)) / math.sqrt(N))
     return np.array(out)
+
+
+def multiplicative_order(y: int, G: int) -> int:
+    """The period r of f(x) = y^x mod G (smallest r > 0 with y^r = 1 mod G), by stepping through the
+    powers (Sec. V); y must be coprime to G."""
+    if math.gcd(y, G) != 1:
+        raise ValueError("y and G are not coprime")
+    r, v = 1, y % G
+    while v != 1:
+        v = (v * y) % G
+        r += 1
+    return r
+
+
+def shor_probabilities(X: int, r: int) -> np.ndarray:
+    """p_k, k = 0 .. 2^X - 1: the probability to observe |k> in the x-register after the Fourier
+    transform in Shor's algorithm (Sec. V), for a function of period r. From the Fourier
+    representation, the x-values that share f(x0) are x0 + j r, and
+        p_k = 2^{-2X} sum_{x0 < r} | sum_j e^{2 pi i k (x0 + j r) / 2^X} |^2 ,
+    where x0 < c = 2^X - r s (s = floor(2^X / r)) has s + 1 terms and the other r - c residues have s.
+    Each inner sum is a geometric series of ratio e^{2 pi i phi}, phi = (k r mod 2^X) / 2^X, whose
+    squared modulus for t terms is sin^2(pi t phi) / sin^2(pi phi), or t^2 when phi = 0; the products
+    k r and t (k r) are reduced modulo 2^X in exact integer arithmetic before the sines. This sum replaces the printed closed form Eq. Shor5, whose second term carries
+    the wrong sign (with it the p_k do not sum to 1)."""
+    N = 1 << X
+    s = N // r
+    c = N - r * s
+    k = np.arange(N, dtype=np.int64)
+    m = (k * r) % N  # phi = m / N
+
+    def sin2(u):
+        # sin^2(pi u / N) for integers u: periodic in u with period N and symmetric under u -> N - u,
+        # so the sine is taken at an argument in [0, pi/2]
+        u = u % N
+        return np.sin(np.pi * np.minimum(u, N - u) / N) ** 2
+
+    zero = m == 0
+    safe = np.where(zero, 1.0, sin2(m))
+
+    def geo(t):
+        return np.where(zero, float(t) ** 2, sin2(t * m) / safe)
+
+    return (c * geo(s + 1) + (r - c) * geo(s)) / float(N) ** 2
+
+
+def shor_expectations(X: int, r: int) -> np.ndarray:
+    """<Q_i> = sum_k p_k bit_i(k), i = 0 .. X-1 (Eq. Shor7)."""
+    p = shor_probabilities(X, r)
+    k = np.arange(1 << X, dtype=np.int64)
+    return np.array([float(np.sum(p[((k >> i) & 1) == 1])) for i in range(X)])

@@ -275,3 +275,30 @@ void or_marginals(const double *a, int L, double *q)
     free(p);
     free(sel);
 }
+
+/* Sec. V (Shor's algorithm): the conditional operation that computes f(x) = y^x mod G into the
+ * f-register, written as the permutation |x>|z> -> |x>|z XOR f(x)> of basis states (x = the bits
+ * xf .. xf+xq-1 of the index, z = the bits ff .. ff+fq-1). The powers come from their definition,
+ * f(0) = 1 mod G and f(x+1) = f(x) y mod G; then every pair of indices the map exchanges is swapped
+ * once, from its smaller index. */
+void or_modexp(double *a, int L, int xf, int xq, int ff, int fq, uint64_t y, uint64_t G)
+{
+    const int64_t D = (int64_t)1 << L;
+    const int64_t X = (int64_t)1 << xq;
+    uint64_t *f = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)X);
+    f[0] = 1 % G;
+    for (int64_t x = 1; x < X; ++x) f[x] = (f[x - 1] * (y % G)) % G;
+    (void)fq;
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < D; ++i) {
+        const int64_t x = (i >> xf) & (X - 1);
+        const int64_t m = i ^ (int64_t)(f[x] << ff);
+        if (m <= i) continue;
+        double tr = a[2 * i], ti = a[2 * i + 1];
+        a[2 * i] = a[2 * m];
+        a[2 * i + 1] = a[2 * m + 1];
+        a[2 * m] = tr;
+        a[2 * m + 1] = ti;
+    }
+    free(f);
+}

@@ -123,6 +123,11 @@ class State:
         check(lib().qsim_apply_fused(self.handle, k, (ctypes.c_int * k)(*q),
                                      flat.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
 
+    def apply_modexp(self, x_first: int, x_qubits: int, f_first: int, f_qubits: int, y: int, G: int):
+        """|x>|z> -> |x>|z XOR (y^x mod G)> (Shor's conditional operation; returns when done)."""
+        check(lib().qsim_apply_modexp(self.handle, int(x_first), int(x_qubits), int(f_first), int(f_qubits),
+                                      int(y), int(G)))
+
     # -- reductions
     def norm(self) -> float:
         v = ctypes.c_double()

@@ -82,6 +82,7 @@ SIGNATURES = {
     "qsim_apply_phase": (_i32, [_vp, _u64, _i32, _f64]),
     "qsim_apply_swap": (_i32, [_vp, _u64, _i32, _i32]),
     "qsim_apply_fused": (_i32, [_vp, _i32, ctypes.POINTER(_i32), _dp]),
+    "qsim_apply_modexp": (_i32, [_vp, _i32, _i32, _i32, _i32, _u64, _u64]),
     "qsim_norm": (_i32, [_vp, _dp]),
     "qsim_probs": (_i32, [_vp, _vp, _i32]),
     "qsim_marginals": (_i32, [_vp, _dp]),

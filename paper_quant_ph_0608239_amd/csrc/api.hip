@@ -318,6 +318,20 @@ int qsim_apply_swap(qsim_state *s, uint64_t control_mask, int q0, int q1)
     return launch_swap(s, make_index_map(control_mask | b0 | b1, control_mask | b0), b0 | b1);
 }
 
+int qsim_apply_modexp(qsim_state *s, int x_first, int x_qubits, int f_first, int f_qubits, uint64_t y, uint64_t G)
+{
+    if (int rc = check_state(s)) return rc;
+    if (x_qubits < 1 || x_qubits > 30 || f_qubits < 1 || f_qubits > 32)
+        return set_error(QSIM_EINVAL, "modexp: register sizes out of range (x: 1..30, f: 1..32 qubits)");
+    if (x_first < 0 || f_first < 0 || x_first + x_qubits > s->n || f_first + f_qubits > s->n)
+        return set_error(QSIM_EINVAL, "modexp: a register extends beyond the state");
+    if (!(x_first + x_qubits <= f_first || f_first + f_qubits <= x_first))
+        return set_error(QSIM_EINVAL, "modexp: the x- and f-registers overlap");
+    if (G < 2 || G > (uint64_t(1) << f_qubits) || G > 0xffffffffull)
+        return set_error(QSIM_EINVAL, "modexp: need 2 <= G <= 2^f_qubits and G < 2^32");
+    return launch_modexp(s, x_first, x_qubits, f_first, y, G);
+}
+
 int qsim_apply_fused(qsim_state *s, int k, const int *qubits, const double *U)
 {
     if (int rc = check_state(s)) return rc;

@@ -70,6 +70,24 @@ double touched(const qsim_gate &g, int n)
     return full;
 }
 
+// arithmetic of one gate applied as a 2x2 update: 14 flops per touched amplitude for a dense 2x2
+// (two complex products and a complex sum), 6 for a phase factor, 0 for a permutation or an exact
+// sign change
+double valu_flops(const qsim_gate &g, int n)
+{
+    const double t = touched(g, n);
+    if (g.op == QSIM_OP_SWAP) return 0.0;
+    if (g.op == QSIM_OP_PHASE || g.op == QSIM_OP_RZ) return 6.0 * t;
+    double u[8];
+    if (gate_matrix(g, u)) return 6.0 * t;
+    switch (classify(u)) {
+    case Kind::Swap: return 0.0;
+    case Kind::Phase1: return (u[6] == -1.0 && u[7] == 0.0) ? 0.0 : 6.0 * t;
+    case Kind::Diag: return 6.0 * t;
+    default: return 14.0 * t;
+    }
+}
+
 using cd = std::complex<double>;
 
 // apply one gate to the 2^m x 2^m matrix M (columns = basis inputs) over the block's local qubits
@@ -194,6 +212,7 @@ static int build_fused(qsim_plan *p, const std::vector<qsim_gate> &gates, int km
             st.g = gates[g0];
             p->steps.push_back(st);
             p->info.alg_bytes += 2.0 * touched(gates[g0], n) * amp_bytes(p->dtype);
+            p->info.alg_flops += valu_flops(gates[g0], n);
             continue;
         }
         std::vector<int> qs;
@@ -221,7 +240,6 @@ static int build_fused(qsim_plan *p, const std::vector<qsim_gate> &gates, int km
             st.wofs = wtable.size();
             wtable.resize(wtable.size() + bytes);
             build_wfrag_host(m, p->dtype, U.data(), wtable.data() + st.wofs);
-            p->info.alg_flops += 8.0 * std::ldexp(1.0, n + m);
         } else if (m <= 3) {
             st.U = std::move(U);
         } else {
@@ -229,6 +247,7 @@ static int build_fused(qsim_plan *p, const std::vector<qsim_gate> &gates, int km
         }
         p->steps.push_back(std::move(st));
         p->info.alg_bytes += 2.0 * std::ldexp(1.0, n) * amp_bytes(p->dtype);
+        p->info.alg_flops += 8.0 * std::ldexp(1.0, n + m);
     }
     if (!wtable.empty()) {
         QSIM_HIP(hipMalloc(&p->dev_w, wtable.size()));
@@ -339,11 +358,14 @@ int qsim_plan_create(int n, int dtype, const qsim_gate *gates, int64_t ngates, c
             st.g = g;
             p->steps.push_back(st);
             p->info.alg_bytes += 2.0 * touched(g, n) * amp_bytes(dtype);
+            p->info.alg_flops += valu_flops(g, n);
         }
     } else if (o.method == QSIM_PLAN_FUSED) {
         rc = build_fused(p, gl, o.fuse_k);
     } else {
         rc = staged_build(n, dtype, gl, o.lds_qubits, o.lds_regs, &p->staged, &p->info);
+        if (rc == QSIM_OK)
+            for (const qsim_gate &g : gl) p->info.alg_flops += valu_flops(g, n);
     }
     if (rc) {
         qsim_plan_free(p);

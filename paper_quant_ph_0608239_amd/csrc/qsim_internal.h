@@ -99,6 +99,8 @@ int launch_diag(qsim_state *s, const IndexMap &map, int target, const double d[4
 int launch_swap(qsim_state *s, const IndexMap &map, uint64_t flip);
 // fill with |x>
 int launch_set_basis(qsim_state *s, uint64_t x);
+// |x>|z> -> |x>|z XOR (y^x mod G)> (arguments checked by the caller)
+int launch_modexp(qsim_state *s, int x_first, int x_qubits, int f_first, uint64_t y, uint64_t G);
 // dense k-qubit gate
 int launch_fused(qsim_state *s, int k, const int *qubits, const double *U);
 

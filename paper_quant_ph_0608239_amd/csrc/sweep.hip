@@ -339,6 +339,39 @@ __global__ __launch_bounds__(kBlock) void k_set_basis(T *__restrict__ a, uint64_
     }
 }
 
+// Powers f(x) = y^x mod G for x < count by square and multiply (G < 2^32, so every product of two
+// residues fits 64 bits).
+__global__ __launch_bounds__(kBlock) void k_powmod_table(uint32_t *__restrict__ f, uint64_t count, uint64_t y, uint64_t G)
+{
+    for (uint64_t x = uint64_t(blockIdx.x) * kBlock + threadIdx.x; x < count; x += uint64_t(gridDim.x) * kBlock) {
+        uint64_t r = 1 % G, b = y % G, e = x;
+        while (e) {
+            if (e & 1) r = r * b % G;
+            b = b * b % G;
+            e >>= 1;
+        }
+        f[x] = uint32_t(r);
+    }
+}
+
+// |x>|z> -> |x>|z XOR f(x)>: a permutation of basis states made of disjoint exchanges; the thread of
+// the smaller index of each exchanged pair moves both amplitudes (no arithmetic, bit-exact).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_xor_permute(T *__restrict__ a, uint64_t namps, const uint32_t *__restrict__ f,
+                                                        int x_first, uint64_t xmask, int f_first)
+{
+    using C = typename Vec<T>::C;
+    C *ac = reinterpret_cast<C *>(a);
+    for (uint64_t i = uint64_t(blockIdx.x) * kBlock + threadIdx.x; i < namps; i += uint64_t(gridDim.x) * kBlock) {
+        const uint64_t v = f[(i >> x_first) & xmask];
+        const uint64_t j = i ^ (v << f_first);
+        if (j <= i) continue;
+        const C ai = ac[i], aj = ac[j];
+        ac[i] = aj;
+        ac[j] = ai;
+    }
+}
+
 inline unsigned grid_for(uint64_t items, uint64_t per_block)
 {
     uint64_t g = (items + per_block - 1) / per_block;
@@ -501,6 +534,29 @@ int launch_diag(qsim_state *s, const IndexMap &map, int target, const double d[4
 int launch_swap(qsim_state *s, const IndexMap &map, uint64_t flip)
 {
     return s->dtype == QSIM_C128 ? swap_t<double>(s, map, flip) : swap_t<float>(s, map, flip);
+}
+
+int launch_modexp(qsim_state *s, int x_first, int x_qubits, int f_first, uint64_t y, uint64_t G)
+{
+    const uint64_t X = uint64_t(1) << x_qubits;
+    uint32_t *f = nullptr;
+    QSIM_HIP(hipMalloc(&f, X * sizeof(uint32_t)));
+    hipLaunchKernelGGL(k_powmod_table, dim3(grid_for(X, kBlock)), dim3(kBlock), 0, s->stream, f, X, y, G);
+    hipError_t e = hipGetLastError();
+    const uint64_t N = dim(s->n);
+    if (e == hipSuccess) {
+        if (s->dtype == QSIM_C128)
+            hipLaunchKernelGGL(k_xor_permute<double>, dim3(grid_for(N, kBlock * 4)), dim3(kBlock), 0, s->stream,
+                               static_cast<double *>(s->data), N, f, x_first, X - 1, f_first);
+        else
+            hipLaunchKernelGGL(k_xor_permute<float>, dim3(grid_for(N, kBlock * 4)), dim3(kBlock), 0, s->stream,
+                               static_cast<float *>(s->data), N, f, x_first, X - 1, f_first);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);  // the table is freed below
+    (void)hipFree(f);
+    QSIM_HIP(e);
+    return QSIM_OK;
 }
 
 int launch_set_basis(qsim_state *s, uint64_t x)

@@ -21,6 +21,7 @@ Circuit text format (each consumer has its own parser)::
     CNOT c t | CZ c t | CPHASE c t phi | CRK c t k | CRKDG c t k | CV c t phi
     TOFFOLI c1 c2 t
     QSWAP a b                  quantum swap of two qubits
+    MODEXP xf xq ff fq y G     |x>|z> -> |x>|z XOR (y^x mod G)>, x = qubits xf..xf+xq-1, z = ff..ff+fq-1
 
 Qubit q is bit q of the amplitude index (qubit 0 = least significant bit). For controlled gates
 the control(s) come first and the target last.
@@ -34,6 +35,7 @@ __all__ = [
     "qft_lines", "iqft_lines", "qft_circuit", "ripple_adder_circuit", "adder_operands",
     "qft_adder_circuit", "gaussian_state", "random_state", "batch_circuits", "hexf",
     "circuit_text", "count_gates", "shor_circuit_layout", "inverse_lines", "haar_2x2", "u_line",
+    "SHOR_CASES", "shor_parts", "shor_circuit", "PAPER_ADDERS",
 ]
 
 
@@ -289,6 +291,12 @@ def qft_adder_circuit(values: list[int], m: int) -> tuple[str, dict]:
         "n": n, "target": tgt, "sum": sum(values) % (2 ** m)}
 
 
+# the register adders of the paper's runs: (values, m) with the printed operation counts N_O
+# (Fig. adder; App. B tables)
+PAPER_ADDERS = (((1365, 682), 11, None), ((292, 585, 1170), 11, 286), ((26214, 104857), 17, 493),
+                ((7, 9, 19, 35, 65), 7, 194), ((781, 1054, 3296), 12, 342))
+
+
 # --------------------------------------------------------------------------------------------
 # Shor's period finding: register layout (Eq. Shor0); the modular exponentiation is input data
 # --------------------------------------------------------------------------------------------
@@ -298,6 +306,28 @@ def shor_circuit_layout(L: int, X: int, G: int, y: int) -> dict:
     if G >= 2 ** F or not (G * G <= 2 ** X <= 2 * G * G):
         raise ValueError("register sizes violate G^2 <= 2^X <= 2 G^2 or G < 2^F")
     return {"L": L, "X": X, "F": F, "G": G, "y": y}
+
+
+# (L, X, G, y) of the paper's Shor runs (Table Shortab)
+SHOR_CASES = ((24, 16, 247, 194), (33, 22, 1961, 1698), (33, 22, 2047, 617), (36, 24, 4087, 1392),
+              (36, 24, 4033, 1693))
+
+
+def shor_parts(L: int, X: int, G: int, y: int) -> tuple[str, tuple, str]:
+    """Shor's period finding in three parts: Hadamard on every x-register qubit; the modular
+    exponentiation (xf, xq, ff, fq, y, G); the QFT of the x-register (with its bit-reversal swaps,
+    so that bit i of the final x-register value is qubit i)."""
+    lay = shor_circuit_layout(L, X, G, y)
+    pre = circuit_text(L, [f"H {q}" for q in range(X)], header=[f"Shor L={L} X={X} G={G} y={y}: Hadamards"])
+    post = circuit_text(L, qft_lines(list(range(X))), header=[f"Shor L={L} X={X}: QFT of the x-register"])
+    return pre, (0, X, X, lay["F"], y, G), post
+
+
+def shor_circuit(L: int, X: int, G: int, y: int) -> str:
+    pre, (xf, xq, ff, fq, yy, GG), post = shor_parts(L, X, G, y)
+    body = lambda t: [ln for ln in t.splitlines() if ln and not ln.startswith(("!", "QUBITS"))]
+    return circuit_text(L, body(pre) + [f"MODEXP {xf} {xq} {ff} {fq} {yy} {GG}"] + body(post),
+                        header=[f"Shor L={L} X={X} G={G} y={y}"])
 
 
 # --------------------------------------------------------------------------------------------

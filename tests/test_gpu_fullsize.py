@@ -225,6 +225,9 @@ def test_brickwork_33q_staged_equals_fused_on_samples(q):
 # ----------------------------------------------------------------------------------------------
 # Complex64 brickwork with FP64 renormalisation after every 10 layers
 # ----------------------------------------------------------------------------------------------
+C64_SEED = 31  # the complex64 brickwork uses its own seed
+
+
 def run_renormalised(q, s, n, layers, method, every=10, lds=0, regs=0):
     """Layers in groups of `every`, each group one plan, FP64 renormalisation after each group.
     Returns the norms measured before each renormalisation."""
@@ -232,7 +235,7 @@ def run_renormalised(q, s, n, layers, method, every=10, lds=0, regs=0):
     s.set_basis(0)
     for a in range(0, layers, every):
         b = min(layers, a + every)
-        c = q.parse_circuit(wl.brickwork_circuit(n, layers, seed=21, layer_range=(a, b)))
+        c = q.parse_circuit(wl.brickwork_circuit(n, layers, seed=C64_SEED, layer_range=(a, b)))
         p = plan_for(q, c, "c64", method, lds, regs)
         p.execute(s)
         p.close()
@@ -244,7 +247,7 @@ def run_renormalised(q, s, n, layers, method, every=10, lds=0, regs=0):
 @pytest.fixture(scope="module")
 def brick28_ref(oracle_mod):
     say("brick28: FP64 oracle on the 28-qubit brickwork (20 layers)")
-    return oracle_mod.run_circuit(wl.brickwork_circuit(28, 20, seed=21))
+    return oracle_mod.run_circuit(wl.brickwork_circuit(28, 20, seed=C64_SEED))
 
 
 @pytest.mark.parametrize("method", ["fused", "staged"])
@@ -278,7 +281,7 @@ def test_brickwork_c64_34q_norm_drift_and_uncompute(q, method):
         norms = run_renormalised(q, s, n, 20, method)
         assert all(abs(x - 1.0) <= 1e-4 for x in norms), norms
         assert abs(s.norm() - 1.0) <= 1e-6
-        ci = q.parse_circuit(inverse_text(wl.brickwork_circuit(n, 20, seed=21)))
+        ci = q.parse_circuit(inverse_text(wl.brickwork_circuit(n, 20, seed=C64_SEED)))
         pi = plan_for(q, ci, "c64", method)
         pi.execute(s)
         pi.close()
@@ -319,4 +322,31 @@ def test_batch_2048_sampled_circuits_vs_oracle(q, oracle_mod, dtype):
     finally:
         b.close()
         del b
+        release()
+
+
+@pytest.mark.timeout(1200)
+def test_batch_2048_every_circuit_vs_oracle(q, oracle_mod):
+    """Every one of the 2048 circuits, in both precisions, against the oracle run on that circuit."""
+    texts = wl.batch_circuits(count=2048, nmin=10, nmax=22, depth=50, seed=41)
+    b64 = q.Batch(texts, "c64", use_graph=False)
+    b128 = q.Batch(texts, "c128", use_graph=False)
+    try:
+        say("batch2048 every circuit: launching both precisions")
+        b64.run()
+        b128.run()
+        worst128 = worst64 = 0.0
+        for i, t in enumerate(texts):
+            ref = oracle_mod.run_circuit(t)
+            d = float(np.max(np.abs(b128.download(i).astype(np.complex128) - ref)))
+            f = float(oracle_mod.infidelity(b64.download(i).astype(np.complex128), ref))
+            worst128, worst64 = max(worst128, d), max(worst64, f)
+            assert d <= TOL128, (i, d)
+            assert f <= TOL64_FID, (i, f)
+            if i % 256 == 255:
+                say(f"  {i + 1} circuits checked: worst max|d| (c128) = {worst128:.3e}, worst 1-F (c64) = {worst64:.3e}")
+    finally:
+        b64.close()
+        b128.close()
+        del b64, b128
         release()
