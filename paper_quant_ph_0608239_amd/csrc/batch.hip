@@ -30,7 +30,8 @@ template <typename T, int LOG_E, int LOG_T, int MINW>
 __global__ __launch_bounds__(1 << LOG_T, MINW) void k_batch(T *__restrict__ pool, const BatchCirc *__restrict__ circs,
                                                             const int *__restrict__ order, int count,
                                                             const SPass *__restrict__ passes, const SStage *__restrict__ stages,
-                                                            const SOp *__restrict__ ops, uint64_t *__restrict__ t_claim,
+                                                            const SRound *__restrict__ rounds, const SOp *__restrict__ ops,
+                                                            uint64_t *__restrict__ t_claim,
                                                             uint64_t *__restrict__ t_done)
 {
     using C = typename Vec<T>::C;
@@ -46,7 +47,7 @@ __global__ __launch_bounds__(1 << LOG_T, MINW) void k_batch(T *__restrict__ pool
         const uint64_t nblocks = uint64_t(1) << (bc.n_eff - M);
         for (int p = bc.pass_begin; p < bc.pass_end; ++p) {
             const SPass pass = passes[p];
-            for (uint64_t b = 0; b < nblocks; ++b) run_block<T, LOG_E, LOG_T>(a, pass, b, stages, ops, lds, p == bc.pass_begin);
+            for (uint64_t b = 0; b < nblocks; ++b) run_block<T, LOG_E, LOG_T>(a, pass, b, stages, rounds, ops, lds, p == bc.pass_begin);
             // the next pass reads, from other threads of this workgroup, what this one wrote:
             // a workgroup-scope barrier (release/acquire) orders it; all threads share the CU's L1
             __syncthreads();
@@ -72,6 +73,7 @@ struct qsim_batch {
     int *d_order = nullptr;
     SPass *d_passes = nullptr;
     SStage *d_stages = nullptr;
+    SRound *d_rounds = nullptr;
     SOp *d_ops = nullptr;
     uint64_t *d_tclaim = nullptr, *d_tdone = nullptr;
     int grid = 0;
@@ -95,7 +97,7 @@ template <typename T, int LE, int LT, int MW> int batch_grid(int *grid)
 template <typename T, int LE, int LT, int MW> int batch_launch(qsim_batch *b)
 {
     hipLaunchKernelGGL((k_batch<T, LE, LT, MW>), dim3(b->grid), dim3(1 << LT), 0, b->stream, static_cast<T *>(b->pool),
-                       b->d_circs, b->d_order, b->count, b->d_passes, b->d_stages, b->d_ops, b->d_tclaim, b->d_tdone);
+                       b->d_circs, b->d_order, b->count, b->d_passes, b->d_stages, b->d_rounds, b->d_ops, b->d_tclaim, b->d_tdone);
     QSIM_HIP(hipGetLastError());
     return QSIM_OK;
 }
@@ -177,6 +179,7 @@ int qsim_batch_create(int count, const int *nqubits, const int64_t *offsets, con
     b->stream = static_cast<hipStream_t>(stream);
     std::vector<SPass> passes;
     std::vector<SStage> stages;
+    std::vector<SRound> rounds;
     std::vector<SOp> ops;
     uint64_t slot = 0;
     for (int c = 0; c < count; ++c) {
@@ -191,7 +194,7 @@ int qsim_batch_create(int count, const int *nqubits, const int64_t *offsets, con
             }
         b->total_gates += int64_t(gl.size());
         bc.pass_begin = int(passes.size());
-        if (int rc = staged_schedule(bc.n_eff, dtype, m, log_e, gl, passes, stages, ops)) {
+        if (int rc = staged_schedule(bc.n_eff, dtype, m, log_e, gl, passes, stages, rounds, ops)) {
             delete b;
             return rc;
         }
@@ -221,6 +224,7 @@ int qsim_batch_create(int count, const int *nqubits, const int64_t *offsets, con
     if ((e = hipMalloc(&b->d_order, sizeof(int) * count)) != hipSuccess) return fail(e, "batch: tables");
     if ((e = hipMalloc(&b->d_passes, sizeof(SPass) * passes.size())) != hipSuccess) return fail(e, "batch: tables");
     if ((e = hipMalloc(&b->d_stages, sizeof(SStage) * std::max<size_t>(1, stages.size()))) != hipSuccess) return fail(e, "batch: tables");
+    if ((e = hipMalloc(&b->d_rounds, sizeof(SRound) * std::max<size_t>(1, rounds.size()))) != hipSuccess) return fail(e, "batch: tables");
     if ((e = hipMalloc(&b->d_ops, sizeof(SOp) * std::max<size_t>(1, ops.size()))) != hipSuccess) return fail(e, "batch: tables");
     if ((e = hipMalloc(&b->d_tclaim, sizeof(uint64_t) * count)) != hipSuccess) return fail(e, "batch: timestamps");
     if ((e = hipMalloc(&b->d_tdone, sizeof(uint64_t) * count)) != hipSuccess) return fail(e, "batch: timestamps");
@@ -229,6 +233,8 @@ int qsim_batch_create(int count, const int *nqubits, const int64_t *offsets, con
     if ((e = hipMemcpy(b->d_passes, passes.data(), sizeof(SPass) * passes.size(), hipMemcpyHostToDevice)) != hipSuccess)
         return fail(e, "batch: upload");
     if (!stages.empty() && (e = hipMemcpy(b->d_stages, stages.data(), sizeof(SStage) * stages.size(), hipMemcpyHostToDevice)) != hipSuccess)
+        return fail(e, "batch: upload");
+    if (!rounds.empty() && (e = hipMemcpy(b->d_rounds, rounds.data(), sizeof(SRound) * rounds.size(), hipMemcpyHostToDevice)) != hipSuccess)
         return fail(e, "batch: upload");
     if (!ops.empty()) {
         if ((e = hipMemcpy(b->d_ops, ops.data(), sizeof(SOp) * ops.size(), hipMemcpyHostToDevice)) != hipSuccess) return fail(e, "batch: upload");
@@ -320,6 +326,7 @@ int qsim_batch_free(qsim_batch *b)
     free_dev(b->d_order);
     free_dev(b->d_passes);
     free_dev(b->d_stages);
+    free_dev(b->d_rounds);
     free_dev(b->d_ops);
     free_dev(b->d_tclaim);
     free_dev(b->d_tdone);

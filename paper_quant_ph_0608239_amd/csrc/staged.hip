@@ -30,29 +30,34 @@ namespace {
 
 template <typename T, int LOG_E, int LOG_T, int MINW>
 __global__ __launch_bounds__(1 << LOG_T, MINW) void k_staged(T *__restrict__ a, const SPass *__restrict__ passp,
-                                                             const SStage *__restrict__ stages, const SOp *__restrict__ ops)
+                                                             const SStage *__restrict__ stages, const SRound *__restrict__ rounds,
+                                                             const SOp *__restrict__ ops)
 {
     using C = typename Vec<T>::C;
     __shared__ C lds[lds_slots<T>(LOG_E + LOG_T)];
     const SPass pass = *passp;
-    run_block<T, LOG_E, LOG_T>(a, pass, blockIdx.x, stages, ops, lds, false);
+    run_block<T, LOG_E, LOG_T>(a, pass, blockIdx.x, stages, rounds, ops, lds, false);
 }
 
 }  // namespace
 
 namespace staged {
-// phase factors of angle-defined operations, evaluated once per plan in FP64 on the device
+// factors of angle-defined diagonal operations, evaluated once per plan in FP64 on the device, and
+// the FP32 copy of every op's coefficients
 __global__ void k_op_angles(SOp *ops, int nops)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= nops) return;
     SOp &op = ops[i];
     if (op.angles == 1) {
-        sincos(op.theta[0], &op.m[1], &op.m[0]);
+        op.m[0] = 1.0;
+        op.m[1] = 0.0;
+        sincos(op.theta[0], &op.m[3], &op.m[2]);
     } else if (op.angles == 2) {
         sincos(op.theta[0], &op.m[1], &op.m[0]);
         sincos(op.theta[1], &op.m[3], &op.m[2]);
     }
+    for (int k = 0; k < 8; ++k) op.mf[k] = float(op.m[k]);
 }
 }  // namespace staged
 
@@ -67,6 +72,7 @@ struct StagedPlan {
     std::vector<SPass> passes;
     SPass *d_passes = nullptr;
     SStage *d_stages = nullptr;
+    SRound *d_rounds = nullptr;
     SOp *d_ops = nullptr;
 };
 
@@ -131,10 +137,129 @@ bool staged::staged_variant_ok(int dtype, int log_e, int log_t)
     return (log_e == 4 && log_t >= 7) || (log_e == 5 && log_t <= 8);
 }
 
+namespace {
+
+// an op of the stage being built, with what the round placement needs
+struct HOp {
+    bool dense;
+    int lb;             // dense: local bit of the target
+    int target;         // physical target qubit
+    uint64_t controls;  // physical control qubits
+    uint64_t qmask;     // every qubit the gate touches
+    uint64_t gcm;       // condition on non-resident bits
+    uint32_t lcm;       // condition on resident bits (local positions)
+    double m[8];        // dense 2x2, or diag d0 = m[0..1], d1 = m[2..3]
+    double theta[2];
+    int angles;
+};
+
+// two ops of a stage may run in either order
+bool commute(const HOp &a, const HOp &b)
+{
+    if (!a.dense && !b.dense) return true;
+    if (a.dense && !b.dense) return !((b.qmask >> a.target) & 1);
+    if (!a.dense && b.dense) return !((a.qmask >> b.target) & 1);
+    return a.target != b.target && !((b.controls >> a.target) & 1) && !((a.controls >> b.target) & 1);
+}
+
+}  // namespace
+
+// Close a stage: fix its register bits, turn every op's condition into its register part (pair or
+// element masks) and its thread part, and order the ops into rounds. An op goes to the earliest
+// round in which it runs after every earlier op of the stage it does not commute with (within a
+// round: bit 0 ops, ..., bit LOG_E-1 ops, unconditional before conditional, then diagonal ops).
+static void emit_stage(SStage cur, uint32_t rbset, int log_e, int m, const int *localof, const std::vector<HOp> &sops,
+                       std::vector<SStage> &stages, std::vector<SRound> &rounds, std::vector<SOp> &ops)
+{
+    const int E = 1 << log_e;
+    int nrb = __builtin_popcount(rbset);
+    // fill the register bits from the top local bits so the thread bits keep the low ones
+    for (int s = m - 1; s >= 0 && nrb < log_e; --s)
+        if (!((rbset >> s) & 1)) {
+            rbset |= 1u << s;
+            ++nrb;
+        }
+    for (int s = 0, j = 0, jt = 0; s < m; ++s) {
+        if ((rbset >> s) & 1) cur.rb[j++] = uint8_t(s);
+        else cur.tbits[jt++] = uint8_t(s);
+    }
+    auto rank_of = [&](int lb) { return __builtin_popcount(rbset & ((1u << lb) - 1)); };
+    const size_t N = sops.size();
+    std::vector<SOp> rec(N);
+    std::vector<int> key(N), round(N);
+    int nrounds = 0;
+    for (size_t xi = 0; xi < N; ++xi) {
+        const HOp &h = sops[xi];
+        SOp o{};
+        o.lt = -1;
+        o.gcm = h.gcm;
+        uint32_t rsel = 0;  // register part of the condition, over the register index r
+        for (int s = 0; s < m; ++s)
+            if (((h.lcm >> s) & 1) && ((rbset >> s) & 1)) rsel |= 1u << rank_of(s);
+        o.lcm_t = h.lcm & ~rbset;
+        o.angles = h.angles;
+        o.theta[0] = h.theta[0];
+        o.theta[1] = h.theta[1];
+        memcpy(o.m, h.m, sizeof(o.m));
+        if (h.dense) {
+            const int j = rank_of(h.lb);
+            for (int p = 0; p < E / 2; ++p) {
+                const int r = (p & ((1 << j) - 1)) | ((p >> j) << (j + 1));
+                if ((uint32_t(r) & rsel) == rsel) o.pmask |= 1u << p;
+            }
+            const bool cond = o.lcm_t != 0 || rsel != 0 || o.gcm != 0;
+            key[xi] = 2 * j + (cond ? 1 : 0);
+        } else {
+            const bool d0_one = h.angles == 1 || (h.angles == 0 && h.m[0] == 1.0 && h.m[1] == 0.0);
+            const int lt = localof[h.target];
+            if (lt >= 0 && ((rbset >> lt) & 1)) {
+                const int jt = rank_of(lt);
+                for (int r = 0; r < E; ++r) {
+                    if ((uint32_t(r) & rsel) != rsel) continue;
+                    if ((r >> jt) & 1) o.m1 |= 1u << r;
+                    else if (!d0_one) o.m0 |= 1u << r;
+                }
+            } else {
+                for (int r = 0; r < E; ++r)
+                    if ((uint32_t(r) & rsel) == rsel) o.m1 |= 1u << r;
+                if (lt >= 0) {
+                    if (d0_one) o.lcm_t |= 1u << lt;  // only lanes with the target bit set change
+                    else o.lt = lt;
+                } else {
+                    const uint64_t tb = uint64_t(1) << h.target;
+                    if (d0_one) o.gcm |= tb;  // only blocks with the target bit set change
+                    else o.gtb = tb;
+                }
+            }
+            key[xi] = 2 * log_e;
+        }
+        int k = 0;
+        for (size_t y = 0; y < xi; ++y)
+            if (!commute(h, sops[y])) k = std::max(k, key[y] <= key[xi] ? round[y] : round[y] + 1);
+        round[xi] = k;
+        nrounds = std::max(nrounds, k + 1);
+        rec[xi] = o;
+    }
+    cur.round_begin = int(rounds.size());
+    for (int k = 0; k < nrounds; ++k) {
+        SRound rd{};
+        for (int list = 0; list <= 2 * log_e; ++list) {
+            rd.seg[list] = int(ops.size());
+            for (size_t xi = 0; xi < N; ++xi)
+                if (round[xi] == k && key[xi] == list) ops.push_back(rec[xi]);
+        }
+        rd.seg[2 * log_e + 1] = int(ops.size());
+        rounds.push_back(rd);
+    }
+    cur.round_end = int(rounds.size());
+    stages.push_back(cur);
+}
+
 // Schedule `gates` for an n-qubit state into passes of m resident qubits with 2^log_e amplitudes per
-// thread; passes, stages and ops are appended to the given tables (indices are absolute).
+// thread; passes, stages, rounds and ops are appended to the given tables (indices are absolute).
 int staged::staged_schedule(int n, int dtype, int m, int log_e, const std::vector<qsim_gate> &gates,
-                            std::vector<SPass> &passes, std::vector<SStage> &stages, std::vector<SOp> &ops)
+                            std::vector<SPass> &passes, std::vector<SStage> &stages, std::vector<SRound> &rounds,
+                            std::vector<SOp> &ops)
 {
     const int L = dtype == QSIM_C128 ? 4 : 5;  // low run: 2^L amplitudes = 256 bytes
     const size_t G = gates.size();
@@ -142,7 +267,6 @@ int staged::staged_schedule(int n, int dtype, int m, int log_e, const std::vecto
     for (size_t i = 0; i < G; ++i) gi[i] = describe(gates[i]);
     std::vector<char> done(G, 0);
     size_t ndone = 0;
-
 
     while (ndone < G) {
         // --- resident set: the low run, then the targets of the earliest pending non-diagonal gates
@@ -170,9 +294,9 @@ int staged::staged_schedule(int n, int dtype, int m, int log_e, const std::vecto
         SPass ps{};
         ps.m = m;
         int localof[64];
-        for (int q = 0, s = 0; q < n; ++q) {
+        for (int q = 0, s = 0; q < 64; ++q) {
             localof[q] = -1;
-            if ((R >> q) & 1) {
+            if (q < n && ((R >> q) & 1)) {
                 ps.R[s] = uint8_t(q);
                 localof[q] = s++;
             }
@@ -198,130 +322,66 @@ int staged::staged_schedule(int n, int dtype, int m, int log_e, const std::vecto
             if (ok) take.push_back(i);
             else blocked |= g.qmask;
         }
-        // --- stages
+        // --- stages: a stage holds dense ops on at most log_e distinct resident targets (its
+        // register bits) and diagonal ops on any qubits; a quantum swap ends it
         ps.stage_begin = int(stages.size());
+        std::vector<HOp> sops;
         SStage cur{};
+        cur.swap_p = cur.swap_q = -1;
         uint32_t rbset = 0;
         int nrb = 0;
-        cur.op_begin = int(ops.size());
-        cur.swap_p = cur.swap_q = -1;
         auto close_stage = [&]() {
-            // fill the register bits from the top local bits so the thread bits keep the low ones
-            for (int s = m - 1; s >= 0 && nrb < log_e; --s)
-                if (!((rbset >> s) & 1)) {
-                    rbset |= 1u << s;
-                    ++nrb;
-                }
-            int j = 0, jt = 0;
-            for (int s = 0; s < m; ++s) {
-                if ((rbset >> s) & 1) cur.rb[j++] = uint8_t(s);
-                else cur.tbits[jt++] = uint8_t(s);
-            }
-            cur.op_end = int(ops.size());
-            stages.push_back(cur);
+            emit_stage(cur, rbset, log_e, m, localof, sops, stages, rounds, ops);
+            sops.clear();
             cur = SStage{};
-            cur.op_begin = int(ops.size());
             cur.swap_p = cur.swap_q = -1;
             rbset = 0;
             nrb = 0;
         };
-        auto rbit_of = [&](uint32_t lb) {
-            // index of local bit lb among the stage's register bits (fixed at close: ascending)
-            return lb;
-        };
-        (void)rbit_of;
-        std::vector<std::pair<size_t, int>> pending_rbit;  // op index -> local target bit (fixed up at close)
-        auto rank_of = [&](int lb) {  // register-bit index of local bit lb (rank among the sorted RB)
-            int rank = 0;
-            for (int s = 0; s < lb; ++s)
-                if ((rbset >> s) & 1) ++rank;
-            return rank;
-        };
-        auto fix_rbits = [&]() {
-            for (auto &pr : pending_rbit) ops[pr.first].rbit = rank_of(pr.second);
-            pending_rbit.clear();
-            // split every condition of the stage into its register part (as a mask over the
-            // register index r) and its thread part
-            for (size_t oi = size_t(cur.op_begin); oi < ops.size(); ++oi) {
-                SOp &o = ops[oi];
-                o.rsel = 0;
-                for (int s = 0; s < m; ++s)
-                    if (((o.lcm >> s) & 1) && ((rbset >> s) & 1)) o.rsel |= 1u << rank_of(s);
-                o.lcm_t = o.lcm & ~rbset;
-                if (o.type == 3) o.rbit = (o.lt >= 0 && ((rbset >> o.lt) & 1)) ? rank_of(o.lt) : -1;
-            }
-        };
         for (size_t i : take) {
             const GInfo &g = gi[i];
-            SOp op{};
-            op.gcm = g.controls & ~R;
-            op.lcm = local_mask(g.controls);
-            op.lt = -1;
             if (g.kind == G_SWAP) {
-                // ends the current stage as an LDS permutation
                 cur.swap_p = localof[g.target];
                 cur.swap_q = localof[g.target2];
                 cur.swap_lcm = local_mask(g.controls);
                 cur.swap_gcm = g.controls & ~R;
-                // fill RB and close (before fix_rbits uses the final set)
-                for (int s = m - 1; s >= 0 && nrb < log_e; --s)
-                    if (!((rbset >> s) & 1)) {
-                        rbset |= 1u << s;
-                        ++nrb;
-                    }
-                fix_rbits();
                 close_stage();
                 continue;
             }
+            HOp h{};
+            h.target = g.target;
+            h.controls = g.controls;
+            h.qmask = g.qmask;
+            h.gcm = g.controls & ~R;
+            h.lcm = local_mask(g.controls);
+            h.angles = g.angles;
+            h.theta[0] = g.theta[0];
+            h.theta[1] = g.theta[1];
             if (diagonal(g)) {
-                if (g.kind == G_PHASE) {
-                    op.type = 2;
-                    // condition: controls and the target bit are 1
-                    const uint64_t cond = g.controls | (uint64_t(1) << g.target);
-                    op.gcm = cond & ~R;
-                    op.lcm = local_mask(cond);
-                    op.m[0] = g.m[0];
-                    op.m[1] = g.m[1];
+                h.dense = false;
+                if (g.kind == G_PHASE) {  // diag(1, c)
+                    h.m[0] = 1.0;
+                    h.m[1] = 0.0;
+                    h.m[2] = g.m[0];
+                    h.m[3] = g.m[1];
                 } else {
-                    op.type = 3;
-                    if ((R >> g.target) & 1) {
-                        op.lt = localof[g.target];
-                    } else {
-                        op.lt = -1;
-                        op.gtb = uint64_t(1) << g.target;
-                    }
-                    memcpy(op.m, g.m, sizeof(op.m));
+                    memcpy(h.m, g.m, 4 * sizeof(double));
                 }
-                op.angles = g.angles;
-                op.theta[0] = g.theta[0];
-                op.theta[1] = g.theta[1];
-                ops.push_back(op);
-                continue;
-            }
-            // dense or X on a resident target
-            const int lb = localof[g.target];
-            if (!((rbset >> lb) & 1)) {
-                if (nrb == log_e) {
-                    fix_rbits();
-                    close_stage();
-                }
-                rbset |= 1u << lb;
-                ++nrb;
-            }
-            op.type = 0;  // X runs as the 2x2 [[0,1],[1,0]]: products with exact 0/1 coefficients
-            memcpy(op.m, g.m, sizeof(op.m));
-            pending_rbit.push_back({ops.size(), lb});
-            ops.push_back(op);
-        }
-        if (int(ops.size()) > cur.op_begin || int(stages.size()) == ps.stage_begin) {
-            for (int s = m - 1; s >= 0 && nrb < log_e; --s)
-                if (!((rbset >> s) & 1)) {
-                    rbset |= 1u << s;
+            } else {
+                // dense or X on a resident target (X runs as the 2x2 [[0,1],[1,0]]: products with
+                // exact 0/1 coefficients)
+                h.dense = true;
+                h.lb = localof[g.target];
+                memcpy(h.m, g.m, sizeof(h.m));
+                if (!((rbset >> h.lb) & 1)) {
+                    if (nrb == log_e) close_stage();
+                    rbset |= 1u << h.lb;
                     ++nrb;
                 }
-            fix_rbits();
-            close_stage();
+            }
+            sops.push_back(h);
         }
+        if (!sops.empty() || int(stages.size()) == ps.stage_begin) close_stage();
         ps.stage_end = int(stages.size());
         passes.push_back(ps);
         for (size_t i : take) done[i] = 1;
@@ -346,8 +406,9 @@ int staged_build(int n, int dtype, const std::vector<qsim_gate> &gates, int lds_
 
     std::vector<SPass> passes;
     std::vector<SStage> stages;
+    std::vector<SRound> rounds;
     std::vector<SOp> ops;
-    if (int rc = staged_schedule(n, dtype, m, log_e, gates, passes, stages, ops)) return rc;
+    if (int rc = staged_schedule(n, dtype, m, log_e, gates, passes, stages, rounds, ops)) return rc;
     StagedPlan *p = new StagedPlan();
     p->n = n;
     p->dtype = dtype;
@@ -358,10 +419,13 @@ int staged_build(int n, int dtype, const std::vector<qsim_gate> &gates, int lds_
     // one device copy of each pass record, of the stage table and of the op table
     hipError_t e = hipMalloc(&p->d_passes, sizeof(SPass) * passes.size());
     if (e == hipSuccess) e = hipMalloc(&p->d_stages, sizeof(SStage) * std::max<size_t>(1, stages.size()));
+    if (e == hipSuccess) e = hipMalloc(&p->d_rounds, sizeof(SRound) * std::max<size_t>(1, rounds.size()));
     if (e == hipSuccess) e = hipMalloc(&p->d_ops, sizeof(SOp) * std::max<size_t>(1, ops.size()));
     if (e == hipSuccess) e = hipMemcpy(p->d_passes, passes.data(), sizeof(SPass) * passes.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess && !stages.empty())
         e = hipMemcpy(p->d_stages, stages.data(), sizeof(SStage) * stages.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess && !rounds.empty())
+        e = hipMemcpy(p->d_rounds, rounds.data(), sizeof(SRound) * rounds.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess && !ops.empty()) e = hipMemcpy(p->d_ops, ops.data(), sizeof(SOp) * ops.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess && !ops.empty()) {
         hipLaunchKernelGGL(k_op_angles, dim3(unsigned((ops.size() + 255) / 256)), dim3(256), 0, nullptr, p->d_ops, int(ops.size()));
@@ -389,7 +453,7 @@ static int launch_pass(StagedPlan *p, qsim_state *s, size_t i)
     const SPass *dp = p->d_passes + i;
 #define QSIM_STAGED_LAUNCH(T, LE, LT, MW)                                                                  \
     hipLaunchKernelGGL((k_staged<T, LE, LT, MW>), dim3(blocks), dim3(1 << LT), 0, s->stream, static_cast<T *>(s->data), dp, \
-                       p->d_stages, p->d_ops)
+                       p->d_stages, p->d_rounds, p->d_ops)
     const int v = p->log_e * 16 + p->log_t;
     if (p->dtype == QSIM_C128) {
         switch (v) {
@@ -452,6 +516,7 @@ void staged_free(StagedPlan *p)
     if (!p) return;
     if (p->d_passes) (void)hipFree(p->d_passes);
     if (p->d_stages) (void)hipFree(p->d_stages);
+    if (p->d_rounds) (void)hipFree(p->d_rounds);
     if (p->d_ops) (void)hipFree(p->d_ops);
     delete p;
 }

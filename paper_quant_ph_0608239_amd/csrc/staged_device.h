@@ -9,25 +9,34 @@ namespace qsim {
 namespace staged {
 
 constexpr int kMaxM = 14;
+constexpr int kMaxLogE = 5;
 
+// One operation of a stage. Dense ops act on one register bit (the list they sit in says which);
+// diagonal ops multiply register elements by per-lane factors.
 struct SOp {
-    int32_t type;      // 0 dense 2x2, 1 X (swap pairs), 2 conditional phase, 3 diag(d0, d1)
-    int32_t rbit;      // dense / X: register-bit index of the target; diag: register-bit index of
-                       // the target if it is a register bit, else -1
-    int32_t lt;        // diag: local bit of the target, or -1 if the target is outside R
-    uint32_t lcm;      // local condition mask (local index bits that must be 1)
-    uint32_t rsel;     // the part of lcm on register bits, as a mask over the register index r
-    uint32_t lcm_t;    // the part of lcm on thread bits (local bit positions)
-    uint64_t gcm;      // condition mask on the block's non-resident index bits (must be 1)
-    uint64_t gtb;      // diag with a non-resident target: that bit of the index
-    double m[8];       // dense: 2x2; phase: m[0], m[1]; diag: d0 = m[0..1], d1 = m[2..3]
-    double theta[2];   // angle inputs, turned into m[] on the device when angles != 0
-    int32_t angles;    // 1: phase e^{i theta0}; 2: diag (e^{i theta0}, e^{i theta1})
-    int32_t pad;
+    uint32_t pmask;    // dense: pairs p of the register bit that the register part of the condition admits
+    uint32_t lcm_t;    // condition on thread bits: local bit positions that must be 1
+    uint64_t gcm;      // condition on non-resident index bits (must all be 1)
+    uint64_t gtb;      // diag: the target's index bit when the target is not resident, else 0
+    uint32_t m0, m1;   // diag: register elements r that take factor d0 / d1
+    int32_t lt;        // diag: local bit of the target when it is a thread bit, else -1
+    int32_t angles;    // 0: m[] given; 1: d0 = 1, d1 = e^{i theta0}; 2: d0 = e^{i theta0}, d1 = e^{i theta1}
+    double m[8];       // dense: 2x2 row-major (re, im); diag: d0 = m[0..1], d1 = m[2..3]
+    double theta[2];   // angle inputs of the angles != 0 forms
+    float mf[8];       // m rounded to FP32 (complex64 kernels), filled on the device
+    uint64_t pad;
+};
+
+// A round of a stage: for register bit j, the ops [seg[2j], seg[2j+1]) have no condition and run on
+// every pair; the ops [seg[2j+1], seg[2j+2]) have one; then the diagonal ops
+// [seg[2 LOG_E], seg[2 LOG_E + 1]). Dense ops of one round on different bits commute, and every
+// diagonal op of the round runs after them, so this order equals circuit order.
+struct SRound {
+    int32_t seg[2 * kMaxLogE + 2];
 };
 
 struct SStage {
-    int32_t op_begin, op_end;
+    int32_t round_begin, round_end;
     uint8_t rb[8];      // register bits (local bit indices), LOG_E of them, ascending
     uint8_t tbits[8];   // thread bits (the other local bits), LOG_T of them, ascending
     int32_t swap_p;     // stage-end local swap (quantum swap of two resident qubits), -1 if none
@@ -72,110 +81,133 @@ template <typename C> __device__ __forceinline__ void st_nt(C *p, const C &c)
 template <typename T> __device__ __forceinline__ int slot(int e) { return sizeof(T) == 8 ? e + (e >> 4) : e + (e >> 5); }
 template <typename T> __host__ __device__ constexpr int lds_slots(int m) { return (1 << m) + ((1 << m) >> (sizeof(T) == 8 ? 4 : 5)); }
 
+// In-place complex updates. Every output is an accumulation chain whose last step consumes one input
+// that no other chain still needs; that step writes its result into the input's own register
+// (fma_into). The amplitudes then stay in fixed registers across the op loops, and the compiler
+// has no reason to copy the register array between ops. S: the coefficient is wave-uniform and
+// may sit in a scalar register.
+template <bool S> __device__ __forceinline__ void fma_into(double &x, double c, double t)
+{
+    if constexpr (S) asm("v_fma_f64 %0, %1, %0, %2" : "+v"(x) : "s"(c), "v"(t));
+    else asm("v_fma_f64 %0, %1, %0, %2" : "+v"(x) : "v"(c), "v"(t));
+}
+template <bool S> __device__ __forceinline__ void fma_into(float &x, float c, float t)
+{
+    if constexpr (S) asm("v_fma_f32 %0, %1, %0, %2" : "+v"(x) : "s"(c), "v"(t));
+    else asm("v_fma_f32 %0, %1, %0, %2" : "+v"(x) : "v"(c), "v"(t));
+}
+
+// x <- (fr + i fi) x
 template <typename T>
 __device__ __forceinline__ void cmul(typename Vec<T>::C &x, T fr, T fi)
 {
-    const T r = fr * x.x - fi * x.y;
-    const T i = fr * x.y + fi * x.x;
-    x.x = r;
-    x.y = i;
+    const T ti = fi * x.x;
+    const T tr = -(fi * x.y);
+    fma_into<false>(x.x, fr, tr);
+    fma_into<false>(x.y, fr, ti);
 }
 
-// Element r of a thread in a stage has local index et | er[r]: et (the thread's bits, per lane) and
-// er[r] (the register bits, the same for every lane) occupy disjoint bits. A condition mask lcm
-// therefore splits into a per-lane test on et and a wave-uniform test on er[r], and the padded LDS
-// slot is additive: slot(et | er) = slot(et) + slot(er).
-
-// register-bit ops with a compile-time register bit so that every register index is static.
-// The lane-dependent part of a condition is folded into the coefficients once per op (identity
-// or a phase of 1 on lanes where it fails); the register part (uniform) selects elements with
-// scalar branches, so no element is updated through per-lane selects.
 template <typename T> struct U2 {
     T r[4], i[4];
 };
 
-template <typename T, int E, int RB>
-__device__ __forceinline__ void op_dense(typename Vec<T>::C *x, const uint32_t *er, uint32_t lcm_r, const U2<T> &u)
+// (a, b) <- (u00 a + u01 b, u10 a + u11 b), in place
+template <typename T, bool S>
+__device__ __forceinline__ void pair2x2(typename Vec<T>::C &a, typename Vec<T>::C &b, const U2<T> &u)
 {
+    T t0 = u.r[1] * b.x;
+    T t1 = u.i[0] * a.x;
+    T t2 = u.r[2] * a.x;
+    T t3 = u.r[2] * a.y;
+    t0 = __builtin_fma(-u.i[1], b.y, t0);
+    t1 = __builtin_fma(u.r[1], b.y, t1);
+    t2 = __builtin_fma(-u.i[2], a.y, t2);
+    t3 = __builtin_fma(u.i[2], a.x, t3);
+    t0 = __builtin_fma(-u.i[0], a.y, t0);
+    t1 = __builtin_fma(u.i[1], b.x, t1);
+    t2 = __builtin_fma(-u.i[3], b.y, t2);
+    t3 = __builtin_fma(u.i[3], b.x, t3);
+    fma_into<S>(a.x, u.r[0], t0);
+    fma_into<S>(a.y, u.r[0], t1);
+    fma_into<S>(b.x, u.r[3], t2);
+    fma_into<S>(b.y, u.r[3], t3);
+}
+
+template <typename T> __device__ __forceinline__ const T *coef(const SOp &op);
+template <> __device__ __forceinline__ const double *coef<double>(const SOp &op) { return op.m; }
+template <> __device__ __forceinline__ const float *coef<float>(const SOp &op) { return op.mf; }
+
+// A dense op with no condition on register bit RB: every pair, wave-uniform coefficients.
+template <typename T, int E, int RB>
+__device__ __forceinline__ void op_dense_all(typename Vec<T>::C *x, const SOp &op)
+{
+    const T *c = coef<T>(op);
+    U2<T> u;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        u.r[k] = c[2 * k];
+        u.i[k] = c[2 * k + 1];
+    }
+#pragma unroll
+    for (int r = 0; r < E; ++r)
+        if (!((r >> RB) & 1)) pair2x2<T, true>(x[r], x[r | (1 << RB)], u);
+}
+
+// A dense op with a condition: lanes that fail its thread part keep the identity, pairs outside
+// its register part (pmask, wave-uniform) are skipped.
+template <typename T, int E, int RB>
+__device__ __forceinline__ void op_dense_cond(typename Vec<T>::C *x, const SOp &op, bool lane_ok)
+{
+    const T *c = coef<T>(op);
+    U2<T> u;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const bool dg = (k == 0 || k == 3);
+        u.r[k] = lane_ok ? c[2 * k] : (dg ? T(1) : T(0));
+        u.i[k] = lane_ok ? c[2 * k + 1] : T(0);
+    }
 #pragma unroll
     for (int r = 0; r < E; ++r) {
         if ((r >> RB) & 1) continue;
-        if ((er[r] & lcm_r) != lcm_r) continue;  // uniform
-        const int r1 = r | (1 << RB);
-        const auto a = x[r], b = x[r1];
-        x[r].x = u.r[0] * a.x - u.i[0] * a.y + u.r[1] * b.x - u.i[1] * b.y;
-        x[r].y = u.r[0] * a.y + u.i[0] * a.x + u.r[1] * b.y + u.i[1] * b.x;
-        x[r1].x = u.r[2] * a.x - u.i[2] * a.y + u.r[3] * b.x - u.i[3] * b.y;
-        x[r1].y = u.r[2] * a.y + u.i[2] * a.x + u.r[3] * b.y + u.i[3] * b.x;
+        const int p = (r & ((1 << RB) - 1)) | ((r >> (RB + 1)) << RB);
+        if ((op.pmask >> p) & 1) pair2x2<T, false>(x[r], x[r | (1 << RB)], u);
     }
 }
 
-template <typename T, int E, int RB>
-__device__ __forceinline__ void op_dense_all(typename Vec<T>::C *x, const U2<T> &u)
-{
-#pragma unroll
-    for (int r = 0; r < E; ++r) {
-        if ((r >> RB) & 1) continue;
-        const int r1 = r | (1 << RB);
-        const auto a = x[r], b = x[r1];
-        x[r].x = u.r[0] * a.x - u.i[0] * a.y + u.r[1] * b.x - u.i[1] * b.y;
-        x[r].y = u.r[0] * a.y + u.i[0] * a.x + u.r[1] * b.y + u.i[1] * b.x;
-        x[r1].x = u.r[2] * a.x - u.i[2] * a.y + u.r[3] * b.x - u.i[3] * b.y;
-        x[r1].y = u.r[2] * a.y + u.i[2] * a.x + u.r[3] * b.y + u.i[3] * b.x;
-    }
-}
-
-// phase factor on the elements whose register index r has every bit of SEL set (compile time)
-template <typename T, int E, int SEL>
-__device__ __forceinline__ void op_phase_sel(typename Vec<T>::C *x, T fr, T fi, bool flip)
-{
-    if (flip) {
-#pragma unroll
-        for (int r = 0; r < E; ++r)
-            if ((r & SEL) == SEL) {
-                x[r].x *= fr;
-                x[r].y *= fr;
-            }
-    } else {
-#pragma unroll
-        for (int r = 0; r < E; ++r)
-            if ((r & SEL) == SEL) {
-                const T re = fr * x[r].x - fi * x[r].y;
-                const T im = fr * x[r].y + fi * x[r].x;
-                x[r].x = re;
-                x[r].y = im;
-            }
-    }
-}
-
+// A diagonal op: elements r in m1 take factor f1, those in m0 take f0; with a thread-bit or
+// non-resident target, f1 is chosen per lane (or block) from d0 and d1.
 template <typename T, int E>
-__device__ __forceinline__ void phase_dispatch(int sel, typename Vec<T>::C *x, T fr, T fi, bool flip)
+__device__ __forceinline__ void op_diag(typename Vec<T>::C *x, const SOp &op, uint32_t et, uint64_t base)
 {
-#define QSIM_SEL(k) \
-    case k: if constexpr (k < E) op_phase_sel<T, E, (k < E ? k : 0)>(x, fr, fi, flip); break;
-    switch (sel) {
-        QSIM_SEL(0) QSIM_SEL(1) QSIM_SEL(2) QSIM_SEL(3) QSIM_SEL(4) QSIM_SEL(5) QSIM_SEL(6) QSIM_SEL(7)
-        QSIM_SEL(8) QSIM_SEL(9) QSIM_SEL(10) QSIM_SEL(11) QSIM_SEL(12) QSIM_SEL(13) QSIM_SEL(14) QSIM_SEL(15)
-        QSIM_SEL(16) QSIM_SEL(17) QSIM_SEL(18) QSIM_SEL(19) QSIM_SEL(20) QSIM_SEL(21) QSIM_SEL(22) QSIM_SEL(23)
-        QSIM_SEL(24) QSIM_SEL(25) QSIM_SEL(26) QSIM_SEL(27) QSIM_SEL(28) QSIM_SEL(29) QSIM_SEL(30) QSIM_SEL(31)
-    default: break;
+    const T *c = coef<T>(op);
+    const bool lane_ok = (et & op.lcm_t) == op.lcm_t;
+    T f0r = c[0], f0i = c[1], f1r = c[2], f1i = c[3];
+    if (op.lt >= 0 || op.gtb) {
+        const bool one = op.lt >= 0 ? ((et >> op.lt) & 1) != 0 : (base & op.gtb) != 0;
+        f1r = one ? f1r : f0r;
+        f1i = one ? f1i : f0i;
     }
-#undef QSIM_SEL
-}
-
-template <typename T, int E, int RB>
-__device__ __forceinline__ void op_xswap(typename Vec<T>::C *x, const uint32_t *er, uint32_t lcm_r, bool lane_ok)
-{
+    f0r = lane_ok ? f0r : T(1);
+    f0i = lane_ok ? f0i : T(0);
+    f1r = lane_ok ? f1r : T(1);
+    f1i = lane_ok ? f1i : T(0);
 #pragma unroll
     for (int r = 0; r < E; ++r) {
-        if ((r >> RB) & 1) continue;
-        if ((er[r] & lcm_r) != lcm_r) continue;  // uniform
-        const int r1 = r | (1 << RB);
-        const auto a = x[r], b = x[r1];
-        x[r].x = lane_ok ? b.x : a.x;
-        x[r].y = lane_ok ? b.y : a.y;
-        x[r1].x = lane_ok ? a.x : b.x;
-        x[r1].y = lane_ok ? a.y : b.y;
+        if ((op.m1 >> r) & 1) cmul<T>(x[r], f1r, f1i);
+        if ((op.m0 >> r) & 1) cmul<T>(x[r], f0r, f0i);
+    }
+}
+
+// the ops of one round on register bit J
+template <typename T, int E, int J>
+__device__ __forceinline__ void round_bit(typename Vec<T>::C *x, const SRound &rd, const SOp *__restrict__ ops, uint32_t et,
+                                          uint64_t base)
+{
+    for (int oi = rd.seg[2 * J]; oi < rd.seg[2 * J + 1]; ++oi) op_dense_all<T, E, J>(x, ops[oi]);
+    for (int oi = rd.seg[2 * J + 1]; oi < rd.seg[2 * J + 2]; ++oi) {
+        const SOp &op = ops[oi];
+        if ((base & op.gcm) != op.gcm) continue;  // a control outside R is 0 in this block
+        op_dense_cond<T, E, J>(x, op, (et & op.lcm_t) == op.lcm_t);
     }
 }
 
@@ -184,7 +216,8 @@ __device__ __forceinline__ void op_xswap(typename Vec<T>::C *x, const uint32_t *
 // lds_slots<T>(LOG_E + LOG_T) amplitudes.
 template <typename T, int LOG_E, int LOG_T>
 __device__ __forceinline__ void run_block(T *__restrict__ a, const SPass &pass, uint64_t blk, const SStage *__restrict__ stages,
-                                          const SOp *__restrict__ ops, typename Vec<T>::C *lds, bool init_zero)
+                                          const SRound *__restrict__ rounds, const SOp *__restrict__ ops,
+                                          typename Vec<T>::C *lds, bool init_zero)
 {
     using C = typename Vec<T>::C;
     constexpr int E = 1 << LOG_E;
@@ -232,9 +265,6 @@ __device__ __forceinline__ void run_block(T *__restrict__ a, const SPass &pass, 
 
     for (int si = pass.stage_begin; si < pass.stage_end; ++si) {
         const SStage st = stages[si];
-        uint32_t rbm = 0;
-#pragma unroll
-        for (int j = 0; j < LOG_E; ++j) rbm |= 1u << st.rb[j];
         // thread bits: the local bits that are not register bits, in ascending order
         uint32_t et = 0;
 #pragma unroll
@@ -252,68 +282,17 @@ __device__ __forceinline__ void run_block(T *__restrict__ a, const SPass &pass, 
         C x[E];
 #pragma unroll
         for (int r = 0; r < E; ++r) x[r] = lds[ls + slot<T>(er[r])];
-        for (int oi = st.op_begin; oi < st.op_end; ++oi) {
-            const SOp op = ops[oi];  // one wide scalar load of the whole record
-            if ((base & op.gcm) != op.gcm) continue;  // a control outside R is 0 in this block
-            const uint32_t lcm_r = op.lcm & rbm;
-            const bool lane_ok = (et & op.lcm_t) == op.lcm_t;
-            switch (op.type) {
-            case 0: {
-                U2<T> u;
-#pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    const bool dg = (k == 0 || k == 3);
-                    u.r[k] = lane_ok ? T(op.m[2 * k]) : (dg ? T(1) : T(0));
-                    u.i[k] = lane_ok ? T(op.m[2 * k + 1]) : T(0);
-                }
-                if (op.rsel == 0) {
-                    switch (op.rbit) {
-                    case 0: op_dense_all<T, E, 0>(x, u); break;
-                    case 1: op_dense_all<T, E, 1>(x, u); break;
-                    case 2: op_dense_all<T, E, 2>(x, u); break;
-                    case 3: op_dense_all<T, E, 3>(x, u); break;
-                    default: if constexpr (LOG_E > 4) op_dense_all<T, E, (LOG_E > 4 ? 4 : 0)>(x, u); break;
-                    }
-                    break;
-                }
-                switch (op.rbit) {
-                case 0: op_dense<T, E, 0>(x, er, lcm_r, u); break;
-                case 1: op_dense<T, E, 1>(x, er, lcm_r, u); break;
-                case 2: op_dense<T, E, 2>(x, er, lcm_r, u); break;
-                case 3: op_dense<T, E, 3>(x, er, lcm_r, u); break;
-                default: if constexpr (LOG_E > 4) op_dense<T, E, (LOG_E > 4 ? 4 : 0)>(x, er, lcm_r, u); break;
-                }
-                break;
-            }
-            case 2: {
-                const bool flip = op.m[1] == 0.0 && op.m[0] == -1.0;  // Z, CZ: multiply by -1, exact
-                const T fr = lane_ok ? T(op.m[0]) : T(1), fi = lane_ok ? T(op.m[1]) : T(0);
-                phase_dispatch<T, E>(int(op.rsel), x, fr, fi, flip);
-                break;
-            }
-            case 3: {
-                // diag(d0, d1): elements with target bit 0 get d0, with 1 get d1 (conditions as above)
-                T f0r = T(op.m[0]), f0i = T(op.m[1]), f1r = T(op.m[2]), f1i = T(op.m[3]);
-                if (op.rbit < 0) {  // target on a thread bit or outside R: one factor per lane
-                    const bool one = op.lt >= 0 ? ((et >> op.lt) & 1) != 0 : (base & op.gtb) != 0;
-                    const T fr = lane_ok ? (one ? f1r : f0r) : T(1), fi = lane_ok ? (one ? f1i : f0i) : T(0);
-                    phase_dispatch<T, E>(int(op.rsel), x, fr, fi, false);
-                } else {  // target on register bit j: two selections
-                    if (!lane_ok) {
-                        f0r = f1r = T(1);
-                        f0i = f1i = T(0);
-                    }
-                    const int j = op.rbit;
-#pragma unroll
-                    for (int r = 0; r < E; ++r)
-                        if ((er[r] & lcm_r) == lcm_r) {
-                            const bool one = (r >> j) & 1;
-                            cmul<T>(x[r], one ? f1r : f0r, one ? f1i : f0i);
-                        }
-                }
-                break;
-            }
-            default: break;
+        for (int ri = st.round_begin; ri < st.round_end; ++ri) {
+            const SRound rd = rounds[ri];
+            round_bit<T, E, 0>(x, rd, ops, et, base);
+            round_bit<T, E, 1>(x, rd, ops, et, base);
+            round_bit<T, E, 2>(x, rd, ops, et, base);
+            if constexpr (LOG_E > 3) round_bit<T, E, (LOG_E > 3 ? 3 : 0)>(x, rd, ops, et, base);
+            if constexpr (LOG_E > 4) round_bit<T, E, (LOG_E > 4 ? 4 : 0)>(x, rd, ops, et, base);
+            for (int oi = rd.seg[2 * LOG_E]; oi < rd.seg[2 * LOG_E + 1]; ++oi) {
+                const SOp &op = ops[oi];
+                if ((base & op.gcm) != op.gcm) continue;
+                op_diag<T, E>(x, op, et, base);
             }
         }
         __syncthreads();  // every thread has read this stage's inputs before anyone overwrites LDS
@@ -350,7 +329,7 @@ __device__ __forceinline__ void run_block(T *__restrict__ a, const SPass &pass, 
 
 // host: append the schedule of one circuit (see staged.hip)
 int staged_schedule(int n, int dtype, int m, int log_e, const std::vector<qsim_gate> &gates, std::vector<SPass> &passes,
-                    std::vector<SStage> &stages, std::vector<SOp> &ops);
+                    std::vector<SStage> &stages, std::vector<SRound> &rounds, std::vector<SOp> &ops);
 bool staged_variant_ok(int dtype, int log_e, int log_t);
 __global__ void k_op_angles(SOp *ops, int nops);
 
