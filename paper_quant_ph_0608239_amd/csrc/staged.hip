@@ -231,7 +231,10 @@ static void emit_stage(SStage cur, uint32_t rbset, int log_e, int m, const int *
                     else o.gtb = tb;
                 }
             }
-            key[xi] = 2 * log_e;
+            // a sign flip: d0 = 1 and d1 = -1 exactly, with the target folded into the condition
+            const bool flip = d0_one && h.angles == 0 && h.m[2] == -1.0 && h.m[3] == 0.0 && o.m0 == 0 && o.lt < 0 &&
+                              o.gtb == 0;
+            key[xi] = 2 * log_e + (flip ? 0 : 1);
         }
         int k = 0;
         for (size_t y = 0; y < xi; ++y)
@@ -243,12 +246,12 @@ static void emit_stage(SStage cur, uint32_t rbset, int log_e, int m, const int *
     cur.round_begin = int(rounds.size());
     for (int k = 0; k < nrounds; ++k) {
         SRound rd{};
-        for (int list = 0; list <= 2 * log_e; ++list) {
+        for (int list = 0; list <= 2 * log_e + 1; ++list) {
             rd.seg[list] = int(ops.size());
             for (size_t xi = 0; xi < N; ++xi)
                 if (round[xi] == k && key[xi] == list) ops.push_back(rec[xi]);
         }
-        rd.seg[2 * log_e + 1] = int(ops.size());
+        rd.seg[2 * log_e + 2] = int(ops.size());
         rounds.push_back(rd);
     }
     cur.round_end = int(rounds.size());

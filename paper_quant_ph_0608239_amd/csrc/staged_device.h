@@ -28,11 +28,13 @@ struct SOp {
 };
 
 // A round of a stage: for register bit j, the ops [seg[2j], seg[2j+1]) have no condition and run on
-// every pair; the ops [seg[2j+1], seg[2j+2]) have one; then the diagonal ops
-// [seg[2 LOG_E], seg[2 LOG_E + 1]). Dense ops of one round on different bits commute, and every
-// diagonal op of the round runs after them, so this order equals circuit order.
+// every pair; the ops [seg[2j+1], seg[2j+2]) have one; then the sign flips (diagonal ops whose only
+// factor is -1) [seg[2 LOG_E], seg[2 LOG_E + 1]) and the other diagonal ops
+// [seg[2 LOG_E + 1], seg[2 LOG_E + 2]). Dense ops of one round on different bits commute, diagonal
+// ops commute with each other, and every diagonal op of the round runs after its dense ops, so this
+// order equals circuit order.
 struct SRound {
-    int32_t seg[2 * kMaxLogE + 2];
+    int32_t seg[2 * kMaxLogE + 4];
 };
 
 struct SStage {
@@ -198,6 +200,29 @@ __device__ __forceinline__ void op_diag(typename Vec<T>::C *x, const SOp &op, ui
     }
 }
 
+// A sign flip: elements r in m1 change sign on lanes that meet the condition. The sign bit is
+// toggled with an integer xor (exact, no rounding), the per-element choice is made in scalar
+// registers, so the op runs without branches.
+__device__ __forceinline__ void flip_sign(double &v, uint32_t t)
+{
+    uint2 h = __builtin_bit_cast(uint2, v);
+    h.y ^= t;
+    v = __builtin_bit_cast(double, h);
+}
+__device__ __forceinline__ void flip_sign(float &v, uint32_t t) { v = __builtin_bit_cast(float, __builtin_bit_cast(uint32_t, v) ^ t); }
+
+template <typename T, int E>
+__device__ __forceinline__ void op_flip(typename Vec<T>::C *x, const SOp &op, uint32_t et)
+{
+    const uint32_t lane_sign = (et & op.lcm_t) == op.lcm_t ? 0x80000000u : 0u;
+#pragma unroll
+    for (int r = 0; r < E; ++r) {
+        const uint32_t t = ((op.m1 >> r) & 1) ? lane_sign : 0u;
+        flip_sign(x[r].x, t);
+        flip_sign(x[r].y, t);
+    }
+}
+
 // the ops of one round on register bit J
 template <typename T, int E, int J>
 __device__ __forceinline__ void round_bit(typename Vec<T>::C *x, const SRound &rd, const SOp *__restrict__ ops, uint32_t et,
@@ -290,6 +315,11 @@ __device__ __forceinline__ void run_block(T *__restrict__ a, const SPass &pass, 
             if constexpr (LOG_E > 3) round_bit<T, E, (LOG_E > 3 ? 3 : 0)>(x, rd, ops, et, base);
             if constexpr (LOG_E > 4) round_bit<T, E, (LOG_E > 4 ? 4 : 0)>(x, rd, ops, et, base);
             for (int oi = rd.seg[2 * LOG_E]; oi < rd.seg[2 * LOG_E + 1]; ++oi) {
+                const SOp &op = ops[oi];
+                if ((base & op.gcm) != op.gcm) continue;
+                op_flip<T, E>(x, op, et);
+            }
+            for (int oi = rd.seg[2 * LOG_E + 1]; oi < rd.seg[2 * LOG_E + 2]; ++oi) {
                 const SOp &op = ops[oi];
                 if ((base & op.gcm) != op.gcm) continue;
                 op_diag<T, E>(x, op, et, base);
