@@ -46,8 +46,8 @@ __global__ __launch_bounds__(1 << LOG_T, MINW) void k_batch(T *__restrict__ pool
         T *a = pool + 2 * bc.slot;
         const uint64_t nblocks = uint64_t(1) << (bc.n_eff - M);
         for (int p = bc.pass_begin; p < bc.pass_end; ++p) {
-            const SPass pass = passes[p];
-            for (uint64_t b = 0; b < nblocks; ++b) run_block<T, LOG_E, LOG_T>(a, pass, b, stages, rounds, ops, lds, p == bc.pass_begin);
+            const SPass pass = ldc<SPass>(as_const(passes) + p);
+            for (uint64_t b = 0; b < nblocks; ++b) run_block<T, LOG_E, LOG_T>(a, pass, b, as_const(stages), as_const(rounds), as_const(ops), lds, p == bc.pass_begin);
             // the next pass reads, from other threads of this workgroup, what this one wrote:
             // a workgroup-scope barrier (release/acquire) orders it; all threads share the CU's L1
             __syncthreads();

@@ -28,6 +28,10 @@ using namespace staged;
 
 namespace {
 
+// One pass over the whole state: one workgroup per block of 2^(LOG_E + LOG_T) amplitudes. (A
+// persistent grid that prefetches each workgroup's next block into registers while the current one
+// is processed measured slower on gfx950: the extra registers and the wait for the previous block's
+// stores cost more than the overlap gained.)
 template <typename T, int LOG_E, int LOG_T, int MINW>
 __global__ __launch_bounds__(1 << LOG_T, MINW) void k_staged(T *__restrict__ a, const SPass *__restrict__ passp,
                                                              const SStage *__restrict__ stages, const SRound *__restrict__ rounds,
@@ -35,8 +39,8 @@ __global__ __launch_bounds__(1 << LOG_T, MINW) void k_staged(T *__restrict__ a, 
 {
     using C = typename Vec<T>::C;
     __shared__ C lds[lds_slots<T>(LOG_E + LOG_T)];
-    const SPass pass = *passp;
-    run_block<T, LOG_E, LOG_T>(a, pass, blockIdx.x, stages, rounds, ops, lds, false);
+    const SPass pass = ldc<SPass>(as_const(passp));
+    run_block<T, LOG_E, LOG_T>(a, pass, blockIdx.x, as_const(stages), as_const(rounds), as_const(ops), lds, false);
 }
 
 }  // namespace
@@ -386,6 +390,15 @@ int staged::staged_schedule(int n, int dtype, int m, int log_e, const std::vecto
         }
         if (!sops.empty() || int(stages.size()) == ps.stage_begin) close_stage();
         ps.stage_end = int(stages.size());
+        // direct memory access for the first / last stage when its register bits avoid the low run
+        auto low_free = [&](const SStage &st) {
+            for (int j = 0; j < log_e; ++j)
+                if (st.rb[j] < L) return false;
+            return true;
+        };
+        ps.direct = 0;
+        if (low_free(stages[size_t(ps.stage_begin)])) ps.direct |= 1;
+        if (low_free(stages[size_t(ps.stage_end - 1)]) && stages[size_t(ps.stage_end - 1)].swap_p < 0) ps.direct |= 2;
         passes.push_back(ps);
         for (size_t i : take) done[i] = 1;
         ndone += take.size();
@@ -450,34 +463,35 @@ int staged_build(int n, int dtype, const std::vector<qsim_gate> &gates, int lds_
     return QSIM_OK;
 }
 
+template <typename T, int LE, int LT, int MW>
+static void launch_variant(StagedPlan *p, qsim_state *s, size_t i)
+{
+    hipLaunchKernelGGL((k_staged<T, LE, LT, MW>), dim3(unsigned(dim(p->n - p->m))), dim3(1 << LT), 0, s->stream,
+                       static_cast<T *>(s->data), p->d_passes + i, p->d_stages, p->d_rounds, p->d_ops);
+}
+
 static int launch_pass(StagedPlan *p, qsim_state *s, size_t i)
 {
-    const unsigned blocks = unsigned(dim(p->n - p->m));
-    const SPass *dp = p->d_passes + i;
-#define QSIM_STAGED_LAUNCH(T, LE, LT, MW)                                                                  \
-    hipLaunchKernelGGL((k_staged<T, LE, LT, MW>), dim3(blocks), dim3(1 << LT), 0, s->stream, static_cast<T *>(s->data), dp, \
-                       p->d_stages, p->d_rounds, p->d_ops)
     const int v = p->log_e * 16 + p->log_t;
     if (p->dtype == QSIM_C128) {
         switch (v) {
-        case 3 * 16 + 7: QSIM_STAGED_LAUNCH(double, 3, 7, 4); break;
-        case 3 * 16 + 8: QSIM_STAGED_LAUNCH(double, 3, 8, 4); break;
-        case 3 * 16 + 9: QSIM_STAGED_LAUNCH(double, 3, 9, 3); break;
-        case 4 * 16 + 6: QSIM_STAGED_LAUNCH(double, 4, 6, 2); break;
-        case 4 * 16 + 7: QSIM_STAGED_LAUNCH(double, 4, 7, 2); break;
-        default: QSIM_STAGED_LAUNCH(double, 4, 8, 2); break;
+        case 3 * 16 + 7: launch_variant<double, 3, 7, 4>(p, s, i); break;
+        case 3 * 16 + 8: launch_variant<double, 3, 8, 4>(p, s, i); break;
+        case 3 * 16 + 9: launch_variant<double, 3, 9, 3>(p, s, i); break;
+        case 4 * 16 + 6: launch_variant<double, 4, 6, 2>(p, s, i); break;
+        case 4 * 16 + 7: launch_variant<double, 4, 7, 2>(p, s, i); break;
+        default: launch_variant<double, 4, 8, 2>(p, s, i); break;
         }
     } else {
         switch (v) {
-        case 4 * 16 + 7: QSIM_STAGED_LAUNCH(float, 4, 7, 3); break;
-        case 4 * 16 + 8: QSIM_STAGED_LAUNCH(float, 4, 8, 3); break;
-        case 4 * 16 + 9: QSIM_STAGED_LAUNCH(float, 4, 9, 2); break;
-        case 5 * 16 + 6: QSIM_STAGED_LAUNCH(float, 5, 6, 1); break;
-        case 5 * 16 + 7: QSIM_STAGED_LAUNCH(float, 5, 7, 1); break;
-        default: QSIM_STAGED_LAUNCH(float, 5, 8, 1); break;
+        case 4 * 16 + 7: launch_variant<float, 4, 7, 3>(p, s, i); break;
+        case 4 * 16 + 8: launch_variant<float, 4, 8, 3>(p, s, i); break;
+        case 4 * 16 + 9: launch_variant<float, 4, 9, 2>(p, s, i); break;
+        case 5 * 16 + 6: launch_variant<float, 5, 6, 1>(p, s, i); break;
+        case 5 * 16 + 7: launch_variant<float, 5, 7, 1>(p, s, i); break;
+        default: launch_variant<float, 5, 8, 1>(p, s, i); break;
         }
     }
-#undef QSIM_STAGED_LAUNCH
     QSIM_HIP(hipGetLastError());
     return QSIM_OK;
 }

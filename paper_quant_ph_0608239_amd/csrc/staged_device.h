@@ -51,9 +51,28 @@ struct SStage {
 struct SPass {
     int32_t m;
     int32_t stage_begin, stage_end;
-    int32_t pad;
+    int32_t direct;     // bit 0: the first stage loads its registers straight from memory; bit 1: the
+                        // last stage stores them straight to memory (no LDS round trip). Set when the
+                        // stage's register bits avoid the low run, so that its thread bits keep
+                        // consecutive lanes on consecutive amplitudes
     uint8_t R[16];      // physical bit of local bit s, ascending
 };
+
+// Plan tables are read-only while a pass runs: they are read through constant-address-space
+// pointers, so wave-uniform reads of them become scalar loads whatever the kernel stores elsewhere.
+template <typename T> using cptr = const T __attribute__((address_space(4))) *;
+template <typename T> __device__ __forceinline__ cptr<T> as_const(const T *p) { return (cptr<T>)p; }
+// copy of a table record (word by word, so the compiler can merge the reads into wide scalar loads)
+template <typename S> __device__ __forceinline__ S ldc(cptr<S> p)
+{
+    static_assert(sizeof(S) % 4 == 0, "records are whole words");
+    S v;
+    uint32_t *d = reinterpret_cast<uint32_t *>(&v);
+    const cptr<uint32_t> w = (cptr<uint32_t>)p;
+#pragma unroll
+    for (int i = 0; i < int(sizeof(S) / 4); ++i) d[i] = w[i];
+    return v;
+}
 
 template <typename T> struct Vec;
 template <> struct Vec<double> { using C = double2; };
@@ -225,71 +244,101 @@ __device__ __forceinline__ void op_flip(typename Vec<T>::C *x, const SOp &op, ui
 
 // the ops of one round on register bit J
 template <typename T, int E, int J>
-__device__ __forceinline__ void round_bit(typename Vec<T>::C *x, const SRound &rd, const SOp *__restrict__ ops, uint32_t et,
+__device__ __forceinline__ void round_bit(typename Vec<T>::C *x, const SRound &rd, cptr<SOp> ops, uint32_t et,
                                           uint64_t base)
 {
-    for (int oi = rd.seg[2 * J]; oi < rd.seg[2 * J + 1]; ++oi) op_dense_all<T, E, J>(x, ops[oi]);
+    for (int oi = rd.seg[2 * J]; oi < rd.seg[2 * J + 1]; ++oi) {
+        const SOp op = ldc<SOp>(ops + oi);
+        op_dense_all<T, E, J>(x, op);
+    }
     for (int oi = rd.seg[2 * J + 1]; oi < rd.seg[2 * J + 2]; ++oi) {
-        const SOp &op = ops[oi];
+        const SOp op = ldc<SOp>(ops + oi);
         if ((base & op.gcm) != op.gcm) continue;  // a control outside R is 0 in this block
         op_dense_cond<T, E, J>(x, op, (et & op.lcm_t) == op.lcm_t);
     }
 }
 
-// Process block `blk` of a pass: load it (or generate |0...0> when init_zero is set), run the
-// stages, store it. Called by every thread of a workgroup of 2^LOG_T threads; `lds` holds
-// lds_slots<T>(LOG_E + LOG_T) amplitudes.
-template <typename T, int LOG_E, int LOG_T>
-__device__ __forceinline__ void run_block(T *__restrict__ a, const SPass &pass, uint64_t blk, const SStage *__restrict__ stages,
-                                          const SRound *__restrict__ rounds, const SOp *__restrict__ ops,
-                                          typename Vec<T>::C *lds, bool init_zero)
+// Addressing of a block: block `blk` of a pass holds the 2^M amplitudes whose index bits outside the
+// resident set R equal the bits of blk. In the load/store layout, thread t and element k hold local
+// index k * NT + t, so consecutive threads take consecutive local indices (contiguous runs).
+template <int M>
+__device__ __forceinline__ uint64_t block_base(const SPass &pass, uint64_t blk)
 {
-    using C = typename Vec<T>::C;
-    constexpr int E = 1 << LOG_E;
-    constexpr int NT = 1 << LOG_T;
-    constexpr int M = LOG_E + LOG_T;
-    const int t = threadIdx.x;
-    // block base: insert a zero bit at every resident position (uniform)
-    uint64_t base = blk;
+    uint64_t base = blk;  // insert a zero bit at every resident position (uniform)
 #pragma unroll
     for (int s = 0; s < M; ++s) {
         const int p = pass.R[s];
         const uint64_t lo = base & ((uint64_t(1) << p) - 1);
         base = lo | ((base ^ lo) << 1);
     }
-    // global index of local index k * NT + t = base | dep(t) | dep(k << LOG_T): the lane part is
-    // computed once, the k part is uniform
+    return base;
+}
+template <int LOG_T>
+__device__ __forceinline__ uint64_t lane_part(const SPass &pass, int t)
+{
     uint64_t dt = 0;
 #pragma unroll
     for (int s = 0; s < LOG_T; ++s)
         if ((t >> s) & 1) dt |= uint64_t(1) << pass.R[s];
-    const C *ag = reinterpret_cast<const C *>(a) + (base | dt);
-    C *agw = reinterpret_cast<C *>(a) + (base | dt);
-    auto dk = [&](int k) {  // uniform
-        uint64_t v = 0;
+    return dt;
+}
+template <int LOG_E, int LOG_T>
+__device__ __forceinline__ uint64_t elem_part(const SPass &pass, int k)  // uniform
+{
+    uint64_t v = 0;
 #pragma unroll
-        for (int j = 0; j < LOG_E; ++j)
-            if ((k >> j) & 1) v |= uint64_t(1) << pass.R[LOG_T + j];
-        return v;
-    };
-    // load: consecutive threads take consecutive local indices (contiguous runs in memory)
-    if (init_zero) {
-#pragma unroll
-        for (int k = 0; k < E; ++k) {
-            const bool one = base == 0 && k == 0 && t == 0;
-            lds[slot<T>(k * NT + t)] = C{one ? T(1) : T(0), T(0)};
-        }
-    } else {
-        C v[E];
-#pragma unroll
-        for (int k = 0; k < E; ++k) v[k] = ld_nt(ag + dk(k));
-#pragma unroll
-        for (int k = 0; k < E; ++k) lds[slot<T>(k * NT + t)] = v[k];
-    }
-    __syncthreads();
+    for (int j = 0; j < LOG_E; ++j)
+        if ((k >> j) & 1) v |= uint64_t(1) << pass.R[LOG_T + j];
+    return v;
+}
 
+template <typename T, int LOG_E, int LOG_T>
+__device__ __forceinline__ void load_block(const T *__restrict__ a, const SPass &pass, uint64_t base, uint64_t dt,
+                                           typename Vec<T>::C *v)
+{
+    using C = typename Vec<T>::C;
+    const C *ag = reinterpret_cast<const C *>(a) + (base | dt);
+#pragma unroll
+    for (int k = 0; k < (1 << LOG_E); ++k) v[k] = ld_nt(ag + elem_part<LOG_E, LOG_T>(pass, k));
+}
+
+template <typename T, int LOG_E, int LOG_T>
+__device__ __forceinline__ void regs_to_lds(const typename Vec<T>::C *v, typename Vec<T>::C *lds)
+{
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int k = 0; k < (1 << LOG_E); ++k) lds[slot<T>(k * (1 << LOG_T) + t)] = v[k];
+}
+
+template <typename T, int LOG_E, int LOG_T>
+__device__ __forceinline__ void store_block(T *__restrict__ a, const SPass &pass, uint64_t base, uint64_t dt,
+                                            const typename Vec<T>::C *lds)
+{
+    using C = typename Vec<T>::C;
+    constexpr int E = 1 << LOG_E;
+    const int t = threadIdx.x;
+    C *agw = reinterpret_cast<C *>(a) + (base | dt);
+    C v[E];
+#pragma unroll
+    for (int k = 0; k < E; ++k) v[k] = lds[slot<T>(k * (1 << LOG_T) + t)];
+#pragma unroll
+    for (int k = 0; k < E; ++k) st_nt(agw + elem_part<LOG_E, LOG_T>(pass, k), v[k]);
+}
+
+// Run the stages of a pass on the block held in LDS (load/store layout in, load/store layout out).
+// Every stage reads the block into registers in its own layout, applies its rounds, and writes it
+// back (permuted by the stage-end quantum swap, if any).
+template <typename T, int LOG_E, int LOG_T>
+__device__ __forceinline__ void run_stages(T *__restrict__ a, const SPass &pass, uint64_t base, cptr<SStage> stages,
+                                           cptr<SRound> rounds, cptr<SOp> ops,
+                                           typename Vec<T>::C *lds, bool init_zero)
+{
+    using C = typename Vec<T>::C;
+    constexpr int E = 1 << LOG_E;
+    const int t = threadIdx.x;
+    C x[E];
     for (int si = pass.stage_begin; si < pass.stage_end; ++si) {
-        const SStage st = stages[si];
+        const SStage st = ldc<SStage>(stages + si);
         // thread bits: the local bits that are not register bits, in ascending order
         uint32_t et = 0;
 #pragma unroll
@@ -304,27 +353,55 @@ __device__ __forceinline__ void run_block(T *__restrict__ a, const SPass &pass, 
             er[r] = v;
         }
         const int ls = slot<T>(et);
-        C x[E];
+        const bool first = si == pass.stage_begin, last = si == pass.stage_end - 1;
+        const bool in_mem = first && (pass.direct & 1), out_mem = last && (pass.direct & 2);
+        // memory address of element (t, r) in this stage's layout: base | dep(et) | dep(er[r])
+        uint64_t gt = 0;
+        if (in_mem) {
 #pragma unroll
-        for (int r = 0; r < E; ++r) x[r] = lds[ls + slot<T>(er[r])];
+            for (int j = 0; j < LOG_T; ++j)
+                if ((t >> j) & 1) gt |= uint64_t(1) << pass.R[st.tbits[j]];
+            gt |= base;
+        }
+        auto gr = [&](int r) {  // uniform
+            uint64_t v = 0;
+#pragma unroll
+            for (int j = 0; j < LOG_E; ++j)
+                if ((r >> j) & 1) v |= uint64_t(1) << pass.R[st.rb[j]];
+            return v;
+        };
+        if (in_mem) {
+            const C *ag = reinterpret_cast<const C *>(a) + gt;
+            if (init_zero) {
+#pragma unroll
+                for (int r = 0; r < E; ++r) x[r] = C{(gt | gr(r)) == 0 ? T(1) : T(0), T(0)};
+            } else {
+#pragma unroll
+                for (int r = 0; r < E; ++r) x[r] = ld_nt(ag + gr(r));
+            }
+        } else {
+#pragma unroll
+            for (int r = 0; r < E; ++r) x[r] = lds[ls + slot<T>(er[r])];
+        }
         for (int ri = st.round_begin; ri < st.round_end; ++ri) {
-            const SRound rd = rounds[ri];
+            const SRound rd = ldc<SRound>(rounds + ri);
             round_bit<T, E, 0>(x, rd, ops, et, base);
             round_bit<T, E, 1>(x, rd, ops, et, base);
             round_bit<T, E, 2>(x, rd, ops, et, base);
             if constexpr (LOG_E > 3) round_bit<T, E, (LOG_E > 3 ? 3 : 0)>(x, rd, ops, et, base);
             if constexpr (LOG_E > 4) round_bit<T, E, (LOG_E > 4 ? 4 : 0)>(x, rd, ops, et, base);
             for (int oi = rd.seg[2 * LOG_E]; oi < rd.seg[2 * LOG_E + 1]; ++oi) {
-                const SOp &op = ops[oi];
+                const SOp op = ldc<SOp>(ops + oi);
                 if ((base & op.gcm) != op.gcm) continue;
                 op_flip<T, E>(x, op, et);
             }
             for (int oi = rd.seg[2 * LOG_E + 1]; oi < rd.seg[2 * LOG_E + 2]; ++oi) {
-                const SOp &op = ops[oi];
+                const SOp op = ldc<SOp>(ops + oi);
                 if ((base & op.gcm) != op.gcm) continue;
                 op_diag<T, E>(x, op, et, base);
             }
         }
+        if (out_mem) break;  // stored below, after the loop
         __syncthreads();  // every thread has read this stage's inputs before anyone overwrites LDS
         if (st.swap_p >= 0 && (base & st.swap_gcm) == st.swap_gcm) {
             // stage-end quantum swap of two resident qubits: a permutation of the LDS slots
@@ -343,14 +420,56 @@ __device__ __forceinline__ void run_block(T *__restrict__ a, const SPass &pass, 
         }
         __syncthreads();
     }
-    // store: the same contiguous order as the load
-    {
-        C v[E];
+    if (pass.direct & 2) {
+        // the last stage's registers go straight to memory; storing after the stage loop keeps every
+        // load of the op tables ahead of the first store to the state (scalar loads stay legal)
+        const SStage st = ldc<SStage>(stages + (pass.stage_end - 1));
+        uint64_t gt = base;
 #pragma unroll
-        for (int k = 0; k < E; ++k) v[k] = lds[slot<T>(k * NT + t)];
+        for (int j = 0; j < LOG_T; ++j)
+            if ((t >> j) & 1) gt |= uint64_t(1) << pass.R[st.tbits[j]];
+        C *agw = reinterpret_cast<C *>(a) + gt;
 #pragma unroll
-        for (int k = 0; k < E; ++k) st_nt(agw + dk(k), v[k]);
+        for (int r = 0; r < E; ++r) {
+            uint64_t v = 0;
+#pragma unroll
+            for (int j = 0; j < LOG_E; ++j)
+                if ((r >> j) & 1) v |= uint64_t(1) << pass.R[st.rb[j]];
+            st_nt(agw + v, x[r]);
+        }
     }
+}
+
+// Process block `blk` of a pass: load it (or generate |0...0> when init_zero is set), run the
+// stages, store it. Called by every thread of a workgroup of 2^LOG_T threads; `lds` holds
+// lds_slots<T>(LOG_E + LOG_T) amplitudes.
+template <typename T, int LOG_E, int LOG_T>
+__device__ __forceinline__ void run_block(T *__restrict__ a, const SPass &pass, uint64_t blk, cptr<SStage> stages,
+                                          cptr<SRound> rounds, cptr<SOp> ops,
+                                          typename Vec<T>::C *lds, bool init_zero)
+{
+    using C = typename Vec<T>::C;
+    constexpr int E = 1 << LOG_E;
+    constexpr int NT = 1 << LOG_T;
+    const int t = threadIdx.x;
+    const uint64_t base = block_base<LOG_E + LOG_T>(pass, blk);
+    const uint64_t dt = lane_part<LOG_T>(pass, t);
+    if (!(pass.direct & 1)) {
+        if (init_zero) {
+#pragma unroll
+            for (int k = 0; k < E; ++k) {
+                const bool one = base == 0 && k == 0 && t == 0;
+                lds[slot<T>(k * NT + t)] = C{one ? T(1) : T(0), T(0)};
+            }
+        } else {
+            C v[E];
+            load_block<T, LOG_E, LOG_T>(a, pass, base, dt, v);
+            regs_to_lds<T, LOG_E, LOG_T>(v, lds);
+        }
+        __syncthreads();
+    }
+    run_stages<T, LOG_E, LOG_T>(a, pass, base, stages, rounds, ops, lds, init_zero);
+    if (!(pass.direct & 2)) store_block<T, LOG_E, LOG_T>(a, pass, base, dt, lds);
     // a caller that runs the next block in this workgroup overwrites LDS: every thread must have
     // read its last values first
     __syncthreads();
