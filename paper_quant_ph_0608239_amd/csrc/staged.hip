@@ -212,7 +212,7 @@ static void emit_stage(SStage cur, uint32_t rbset, int log_e, int m, const int *
                 if ((uint32_t(r) & rsel) == rsel) o.pmask |= 1u << p;
             }
             const bool cond = o.lcm_t != 0 || rsel != 0 || o.gcm != 0;
-            key[xi] = 2 * j + (cond ? 1 : 0);
+            key[xi] = kLists * j + (cond ? 3 : 0);
         } else {
             const bool d0_one = h.angles == 1 || (h.angles == 0 && h.m[0] == 1.0 && h.m[1] == 0.0);
             const int lt = localof[h.target];
@@ -238,7 +238,7 @@ static void emit_stage(SStage cur, uint32_t rbset, int log_e, int m, const int *
             // a sign flip: d0 = 1 and d1 = -1 exactly, with the target folded into the condition
             const bool flip = d0_one && h.angles == 0 && h.m[2] == -1.0 && h.m[3] == 0.0 && o.m0 == 0 && o.lt < 0 &&
                               o.gtb == 0;
-            key[xi] = 2 * log_e + (flip ? 0 : 1);
+            key[xi] = kLists * log_e + (flip ? 0 : 1);
         }
         int k = 0;
         for (size_t y = 0; y < xi; ++y)
@@ -247,15 +247,88 @@ static void emit_stage(SStage cur, uint32_t rbset, int log_e, int m, const int *
         nrounds = std::max(nrounds, k + 1);
         rec[xi] = o;
     }
+    // Fuse two-qubit sign flips (CZ) into the dense op that runs last before them in their round on
+    // one of their qubits: the flip then acts as a row negation of that op's 2x2, chosen per pair
+    // (other qubit a register bit), per lane (a thread bit) or per block (a non-resident bit). Every
+    // op executed between the dense op and the flip's place commutes with the flip, so the order
+    // of non-commuting operations is unchanged.
+    const int flip_key = kLists * log_e;
+    std::vector<char> gone(N, 0);
+    auto bit_of_key = [&](int kk) { return kk / kLists; };
+    // condition of a fused flip on the qubit other than the dense op's target
+    auto set_alt = [&](size_t d, uint64_t q2, int j, bool col) {
+        const uint64_t other = q2 & ~(uint64_t(1) << sops[d].target);
+        const int qo = __builtin_ctzll(other);
+        const int lo = localof[qo];
+        SOp &o = rec[d];
+        o.alt_col = col ? 1u : 0u;
+        if (lo >= 0 && ((rbset >> lo) & 1)) {
+            const int jo = rank_of(lo);
+            for (int p = 0; p < E / 2; ++p) {
+                const int r = (p & ((1 << j) - 1)) | ((p >> j) << (j + 1));
+                if ((r >> jo) & 1) o.amask |= 1u << p;
+            }
+            key[d] = kLists * j + 1;
+        } else if (lo >= 0) {
+            o.amask = (1u << (E / 2)) - 1;
+            o.alt_lcm = 1u << lo;
+            key[d] = kLists * j + 2;
+        } else {
+            o.amask = (1u << (E / 2)) - 1;
+            o.galt = other;
+            key[d] = kLists * j + 1;
+        }
+    };
+    // the only dense op of its round on its register bit
+    auto alone = [&](size_t d) {
+        const int j = bit_of_key(key[d]);
+        for (size_t yi = 0; yi < N; ++yi)
+            if (yi != d && !gone[yi] && round[yi] == round[d] && sops[yi].dense && bit_of_key(key[yi]) == j && key[yi] < flip_key)
+                return false;
+        return true;
+    };
+    for (size_t xi = 0; xi < N; ++xi) {
+        if (key[xi] != flip_key || __builtin_popcountll(sops[xi].controls) != 1) continue;
+        const uint64_t q2 = (uint64_t(1) << sops[xi].target) | sops[xi].controls;
+        // the dense op of this round on one of the flip's qubits that executes last
+        long best = -1;
+        for (size_t yi = 0; yi < N; ++yi) {
+            if (gone[yi] || round[yi] != round[xi] || !sops[yi].dense || !((q2 >> sops[yi].target) & 1)) continue;
+            if (best < 0 || key[yi] > key[size_t(best)] || (key[yi] == key[size_t(best)] && yi > size_t(best))) best = long(yi);
+        }
+        if (best < 0) continue;
+        const size_t d = size_t(best);
+        if (key[d] % kLists != 0 || !alone(d)) continue;  // only a plain unconditional op takes a flip
+        set_alt(d, q2, bit_of_key(key[d]), false);
+        gone[xi] = 1;
+    }
+    // the flips left: fuse each into the first dense op executed after it (later rounds of the stage)
+    // on one of its qubits, as a column negation
+    for (size_t xi = 0; xi < N; ++xi) {
+        if (gone[xi] || key[xi] != flip_key || __builtin_popcountll(sops[xi].controls) != 1) continue;
+        const uint64_t q2 = (uint64_t(1) << sops[xi].target) | sops[xi].controls;
+        long best = -1;
+        for (size_t yi = 0; yi < N; ++yi) {
+            if (gone[yi] || round[yi] <= round[xi] || !sops[yi].dense || !((q2 >> sops[yi].target) & 1)) continue;
+            if (best < 0 || round[yi] < round[size_t(best)] ||
+                (round[yi] == round[size_t(best)] && (key[yi] < key[size_t(best)] || (key[yi] == key[size_t(best)] && yi < size_t(best)))))
+                best = long(yi);
+        }
+        if (best < 0) continue;
+        const size_t d = size_t(best);
+        if (key[d] % kLists != 0 || !alone(d)) continue;
+        set_alt(d, q2, bit_of_key(key[d]), true);
+        gone[xi] = 1;
+    }
     cur.round_begin = int(rounds.size());
     for (int k = 0; k < nrounds; ++k) {
         SRound rd{};
-        for (int list = 0; list <= 2 * log_e + 1; ++list) {
+        for (int list = 0; list <= kLists * log_e + 1; ++list) {
             rd.seg[list] = int(ops.size());
             for (size_t xi = 0; xi < N; ++xi)
-                if (round[xi] == k && key[xi] == list) ops.push_back(rec[xi]);
+                if (!gone[xi] && round[xi] == k && key[xi] == list) ops.push_back(rec[xi]);
         }
-        rd.seg[2 * log_e + 2] = int(ops.size());
+        rd.seg[kLists * log_e + 2] = int(ops.size());
         rounds.push_back(rd);
     }
     cur.round_end = int(rounds.size());

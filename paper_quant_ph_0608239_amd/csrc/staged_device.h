@@ -24,17 +24,27 @@ struct SOp {
     double m[8];       // dense: 2x2 row-major (re, im); diag: d0 = m[0..1], d1 = m[2..3]
     double theta[2];   // angle inputs of the angles != 0 forms
     float mf[8];       // m rounded to FP32 (complex64 kernels), filled on the device
-    uint64_t pad;
+    // dense: a sign flip fused into the op (Z on the target, conditioned on one other qubit). Where
+    // the condition holds (pairs in amask, lanes meeting alt_lcm, blocks meeting galt), the op
+    // applies its 2x2 with row 1 negated (the flip follows the op) or, with alt_col, column 1
+    // negated (the flip precedes it)
+    uint64_t galt;
+    uint32_t amask;
+    uint32_t alt_lcm;
+    uint32_t alt_col;
+    uint32_t pad;
 };
 
-// A round of a stage: for register bit j, the ops [seg[2j], seg[2j+1]) have no condition and run on
-// every pair; the ops [seg[2j+1], seg[2j+2]) have one; then the sign flips (diagonal ops whose only
-// factor is -1) [seg[2 LOG_E], seg[2 LOG_E + 1]) and the other diagonal ops
-// [seg[2 LOG_E + 1], seg[2 LOG_E + 2]). Dense ops of one round on different bits commute, diagonal
-// ops commute with each other, and every diagonal op of the round runs after its dense ops, so this
-// order equals circuit order.
+// A round of a stage. For register bit j, four lists of dense ops: [seg[4j], seg[4j+1]) without
+// condition, [seg[4j+1], seg[4j+2]) without condition but with a fused flip chosen per pair or per
+// block, [seg[4j+2], seg[4j+3]) with a fused flip chosen per lane, [seg[4j+3], seg[4j+4]) with a
+// condition. Then the sign flips (diagonal ops whose only factor is -1) [seg[4 LOG_E],
+// seg[4 LOG_E + 1]) and the other diagonal ops [seg[4 LOG_E + 1], seg[4 LOG_E + 2]). Dense ops of
+// one round on different bits commute, diagonal ops commute with each other, and every diagonal op
+// of the round runs after its dense ops, so this order equals circuit order.
+constexpr int kLists = 4;
 struct SRound {
-    int32_t seg[2 * kMaxLogE + 4];
+    int32_t seg[kLists * kMaxLogE + 4];
 };
 
 struct SStage {
@@ -174,6 +184,61 @@ __device__ __forceinline__ void op_dense_all(typename Vec<T>::C *x, const SOp &o
         if (!((r >> RB) & 1)) pair2x2<T, true>(x[r], x[r | (1 << RB)], u);
 }
 
+// A dense op with a fused flip chosen per pair (register bits) or per block: pairs that take it use
+// the 2x2 with row 1 (or column 1) negated; the choice is made on scalar registers.
+template <typename T, int E, int RB>
+__device__ __forceinline__ void op_dense_alt_uniform(typename Vec<T>::C *x, const SOp &op, uint64_t base)
+{
+    const T *c = coef<T>(op);
+    U2<T> u;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        u.r[k] = c[2 * k];
+        u.i[k] = c[2 * k + 1];
+    }
+    const bool blk = (base & op.galt) == op.galt;
+    const int off = op.alt_col ? 1 : 2;  // the entry negated besides u11: u01 (column) or u10 (row)
+#pragma unroll
+    for (int r = 0; r < E; ++r) {
+        if ((r >> RB) & 1) continue;
+        const int p = (r & ((1 << RB) - 1)) | ((r >> (RB + 1)) << RB);
+        const bool neg = blk && ((op.amask >> p) & 1);
+        U2<T> w = u;
+        w.r[1] = (neg && off == 1) ? -u.r[1] : u.r[1];
+        w.i[1] = (neg && off == 1) ? -u.i[1] : u.i[1];
+        w.r[2] = (neg && off == 2) ? -u.r[2] : u.r[2];
+        w.i[2] = (neg && off == 2) ? -u.i[2] : u.i[2];
+        w.r[3] = neg ? -u.r[3] : u.r[3];
+        w.i[3] = neg ? -u.i[3] : u.i[3];
+        pair2x2<T, true>(x[r], x[r | (1 << RB)], w);
+    }
+}
+
+// A dense op with a fused flip chosen per lane (a thread bit): every pair of the lanes that take it
+// uses the 2x2 with row 1 (or column 1) negated.
+template <typename T, int E, int RB>
+__device__ __forceinline__ void op_dense_alt_lane(typename Vec<T>::C *x, const SOp &op, uint32_t et, uint64_t base)
+{
+    const T *c = coef<T>(op);
+    const bool neg = (base & op.galt) == op.galt && (et & op.alt_lcm) == op.alt_lcm;
+    U2<T> w;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        w.r[k] = c[2 * k];
+        w.i[k] = c[2 * k + 1];
+    }
+    const bool n1 = neg && op.alt_col, n2 = neg && !op.alt_col;
+    w.r[1] = n1 ? -w.r[1] : w.r[1];
+    w.i[1] = n1 ? -w.i[1] : w.i[1];
+    w.r[2] = n2 ? -w.r[2] : w.r[2];
+    w.i[2] = n2 ? -w.i[2] : w.i[2];
+    w.r[3] = neg ? -w.r[3] : w.r[3];
+    w.i[3] = neg ? -w.i[3] : w.i[3];
+#pragma unroll
+    for (int r = 0; r < E; ++r)
+        if (!((r >> RB) & 1)) pair2x2<T, false>(x[r], x[r | (1 << RB)], w);
+}
+
 // A dense op with a condition: lanes that fail its thread part keep the identity, pairs outside
 // its register part (pmask, wave-uniform) are skipped.
 template <typename T, int E, int RB>
@@ -247,11 +312,19 @@ template <typename T, int E, int J>
 __device__ __forceinline__ void round_bit(typename Vec<T>::C *x, const SRound &rd, cptr<SOp> ops, uint32_t et,
                                           uint64_t base)
 {
-    for (int oi = rd.seg[2 * J]; oi < rd.seg[2 * J + 1]; ++oi) {
+    for (int oi = rd.seg[kLists * J]; oi < rd.seg[kLists * J + 1]; ++oi) {
         const SOp op = ldc<SOp>(ops + oi);
         op_dense_all<T, E, J>(x, op);
     }
-    for (int oi = rd.seg[2 * J + 1]; oi < rd.seg[2 * J + 2]; ++oi) {
+    for (int oi = rd.seg[kLists * J + 1]; oi < rd.seg[kLists * J + 2]; ++oi) {
+        const SOp op = ldc<SOp>(ops + oi);
+        op_dense_alt_uniform<T, E, J>(x, op, base);
+    }
+    for (int oi = rd.seg[kLists * J + 2]; oi < rd.seg[kLists * J + 3]; ++oi) {
+        const SOp op = ldc<SOp>(ops + oi);
+        op_dense_alt_lane<T, E, J>(x, op, et, base);
+    }
+    for (int oi = rd.seg[kLists * J + 3]; oi < rd.seg[kLists * J + 4]; ++oi) {
         const SOp op = ldc<SOp>(ops + oi);
         if ((base & op.gcm) != op.gcm) continue;  // a control outside R is 0 in this block
         op_dense_cond<T, E, J>(x, op, (et & op.lcm_t) == op.lcm_t);
@@ -390,12 +463,12 @@ __device__ __forceinline__ void run_stages(T *__restrict__ a, const SPass &pass,
             round_bit<T, E, 2>(x, rd, ops, et, base);
             if constexpr (LOG_E > 3) round_bit<T, E, (LOG_E > 3 ? 3 : 0)>(x, rd, ops, et, base);
             if constexpr (LOG_E > 4) round_bit<T, E, (LOG_E > 4 ? 4 : 0)>(x, rd, ops, et, base);
-            for (int oi = rd.seg[2 * LOG_E]; oi < rd.seg[2 * LOG_E + 1]; ++oi) {
+            for (int oi = rd.seg[kLists * LOG_E]; oi < rd.seg[kLists * LOG_E + 1]; ++oi) {
                 const SOp op = ldc<SOp>(ops + oi);
                 if ((base & op.gcm) != op.gcm) continue;
                 op_flip<T, E>(x, op, et);
             }
-            for (int oi = rd.seg[2 * LOG_E + 1]; oi < rd.seg[2 * LOG_E + 2]; ++oi) {
+            for (int oi = rd.seg[kLists * LOG_E + 1]; oi < rd.seg[kLists * LOG_E + 2]; ++oi) {
                 const SOp op = ldc<SOp>(ops + oi);
                 if ((base & op.gcm) != op.gcm) continue;
                 op_diag<T, E>(x, op, et, base);
