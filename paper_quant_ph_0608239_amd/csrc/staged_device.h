@@ -35,8 +35,8 @@ struct SOp {
     uint32_t pad;
 };
 
-// A round of a stage. For register bit j, four lists of dense ops: [seg[4j], seg[4j+1]) without
-// condition, [seg[4j+1], seg[4j+2]) without condition but with a fused flip chosen per pair or per
+// A round of a stage. For register bit j, four lists of dense ops (the first three hold 2x2s with a
+// real first column only): [seg[4j], seg[4j+1]) without condition, [seg[4j+1], seg[4j+2]) without condition but with a fused flip chosen per pair or per
 // block, [seg[4j+2], seg[4j+3]) with a fused flip chosen per lane, [seg[4j+3], seg[4j+4]) with a
 // condition. Then the sign flips (diagonal ops whose only factor is -1) [seg[4 LOG_E],
 // seg[4 LOG_E + 1]) and the other diagonal ops [seg[4 LOG_E + 1], seg[4 LOG_E + 2]). Dense ops of
@@ -164,6 +164,25 @@ __device__ __forceinline__ void pair2x2(typename Vec<T>::C &a, typename Vec<T>::
     fma_into<S>(b.y, u.r[3], t3);
 }
 
+// The same for a 2x2 whose first column is real (u00 and u10 have no imaginary part; u.i[0] and
+// u.i[2] are not read): 12 multiply-adds instead of 16.
+template <typename T, bool S>
+__device__ __forceinline__ void pair2x2_rc(typename Vec<T>::C &a, typename Vec<T>::C &b, const U2<T> &u)
+{
+    T s2 = u.r[2] * a.x;
+    T s3 = u.r[2] * a.y;
+    T s0 = u.r[1] * b.x;
+    T s1 = u.r[1] * b.y;
+    s2 = __builtin_fma(-u.i[3], b.y, s2);
+    s3 = __builtin_fma(u.i[3], b.x, s3);
+    s0 = __builtin_fma(-u.i[1], b.y, s0);
+    s1 = __builtin_fma(u.i[1], b.x, s1);
+    fma_into<S>(a.x, u.r[0], s0);
+    fma_into<S>(a.y, u.r[0], s1);
+    fma_into<S>(b.x, u.r[3], s2);
+    fma_into<S>(b.y, u.r[3], s3);
+}
+
 template <typename T> __device__ __forceinline__ const T *coef(const SOp &op);
 template <> __device__ __forceinline__ const double *coef<double>(const SOp &op) { return op.m; }
 template <> __device__ __forceinline__ const float *coef<float>(const SOp &op) { return op.mf; }
@@ -181,7 +200,7 @@ __device__ __forceinline__ void op_dense_all(typename Vec<T>::C *x, const SOp &o
     }
 #pragma unroll
     for (int r = 0; r < E; ++r)
-        if (!((r >> RB) & 1)) pair2x2<T, true>(x[r], x[r | (1 << RB)], u);
+        if (!((r >> RB) & 1)) pair2x2_rc<T, true>(x[r], x[r | (1 << RB)], u);
 }
 
 // A dense op with a fused flip chosen per pair (register bits) or per block: pairs that take it use
@@ -210,7 +229,7 @@ __device__ __forceinline__ void op_dense_alt_uniform(typename Vec<T>::C *x, cons
         w.i[2] = (neg && off == 2) ? -u.i[2] : u.i[2];
         w.r[3] = neg ? -u.r[3] : u.r[3];
         w.i[3] = neg ? -u.i[3] : u.i[3];
-        pair2x2<T, true>(x[r], x[r | (1 << RB)], w);
+        pair2x2_rc<T, true>(x[r], x[r | (1 << RB)], w);
     }
 }
 
@@ -236,7 +255,7 @@ __device__ __forceinline__ void op_dense_alt_lane(typename Vec<T>::C *x, const S
     w.i[3] = neg ? -w.i[3] : w.i[3];
 #pragma unroll
     for (int r = 0; r < E; ++r)
-        if (!((r >> RB) & 1)) pair2x2<T, false>(x[r], x[r | (1 << RB)], w);
+        if (!((r >> RB) & 1)) pair2x2_rc<T, false>(x[r], x[r | (1 << RB)], w);
 }
 
 // A dense op with a condition: lanes that fail its thread part keep the identity, pairs outside

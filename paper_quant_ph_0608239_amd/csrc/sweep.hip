@@ -32,6 +32,7 @@ typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 template <bool NT, typename W> __device__ __forceinline__ W ldw(const void *p)
 {
+    static_assert(sizeof(W) == 16 || sizeof(W) == 8, "8- or 16-byte words only");
     using V = typename std::conditional<sizeof(W) == 16, u32x4, u32x2>::type;
     V v;
     if constexpr (NT) v = __builtin_nontemporal_load(reinterpret_cast<const V *>(p));
@@ -42,6 +43,7 @@ template <bool NT, typename W> __device__ __forceinline__ W ldw(const void *p)
 }
 template <bool NT, typename W> __device__ __forceinline__ void stw(void *p, const W &w)
 {
+    static_assert(sizeof(W) == 16 || sizeof(W) == 8, "8- or 16-byte words only");
     using V = typename std::conditional<sizeof(W) == 16, u32x4, u32x2>::type;
     V v;
     __builtin_memcpy(&v, &w, sizeof(W));
@@ -412,15 +414,21 @@ int general_t(qsim_state *s, const IndexMap &map, int target, const Mat2 &u)
         return QSIM_OK;
     }
     const bool nt = streaming<T>(map);
-    if (sizeof(T) == 4 && can_vec2(map, pairs)) {
-        const uint64_t items = pairs / 2;
-        if (nt)
-            hipLaunchKernelGGL((k_general<T, 2, kItems, true>), dim3(grid_for(items, kBlock * kItems)), dim3(kBlock), 0, s->stream,
-                               a, items, map, tbit, u);
-        else
-            hipLaunchKernelGGL((k_general<T, 2, kItems, false>), dim3(grid_for(items, kBlock * kItems)), dim3(kBlock), 0,
-                               s->stream, a, items, map, tbit, u);
-    } else {
+    // complex64 moves two neighbouring amplitudes per 16-byte word (VEC = 2); complex128 never does
+    bool vec2 = false;
+    if constexpr (sizeof(T) == 4) {
+        vec2 = can_vec2(map, pairs);
+        if (vec2) {
+            const uint64_t items = pairs / 2;
+            if (nt)
+                hipLaunchKernelGGL((k_general<T, 2, kItems, true>), dim3(grid_for(items, kBlock * kItems)), dim3(kBlock), 0,
+                                   s->stream, a, items, map, tbit, u);
+            else
+                hipLaunchKernelGGL((k_general<T, 2, kItems, false>), dim3(grid_for(items, kBlock * kItems)), dim3(kBlock), 0,
+                                   s->stream, a, items, map, tbit, u);
+        }
+    }
+    if (!vec2) {
         if (nt)
             hipLaunchKernelGGL((k_general<T, 1, kItems, true>), dim3(grid_for(pairs, kBlock * kItems)), dim3(kBlock), 0, s->stream,
                                a, pairs, map, tbit, u);
@@ -437,11 +445,16 @@ int phase_nt(qsim_state *s, const IndexMap &map, const double c[2], DiagMode mod
 {
     const uint64_t items0 = dim(s->n) >> map.npos;
     T *a = static_cast<T *>(s->data);
-    if (sizeof(T) == 4 && can_vec2(map, items0)) {
-        const uint64_t items = items0 / 2;
-        hipLaunchKernelGGL((k_phase<T, 2, kItems, NTV>), dim3(grid_for(items, kBlock * kItems)), dim3(kBlock), 0, s->stream, a, items,
-                           map, c[0], c[1], int(mode));
-    } else {
+    bool vec2 = false;  // complex64 only, as in general_t
+    if constexpr (sizeof(T) == 4) {
+        vec2 = can_vec2(map, items0);
+        if (vec2) {
+            const uint64_t items = items0 / 2;
+            hipLaunchKernelGGL((k_phase<T, 2, kItems, NTV>), dim3(grid_for(items, kBlock * kItems)), dim3(kBlock), 0, s->stream, a,
+                               items, map, c[0], c[1], int(mode));
+        }
+    }
+    if (!vec2) {
         hipLaunchKernelGGL((k_phase<T, 1, kItems, NTV>), dim3(grid_for(items0, kBlock * kItems)), dim3(kBlock), 0, s->stream, a,
                            items0, map, c[0], c[1], int(mode));
     }
@@ -455,11 +468,16 @@ int diag_nt(qsim_state *s, const IndexMap &map, int target, const double d[4], D
     const uint64_t items0 = dim(s->n) >> map.npos;
     T *a = static_cast<T *>(s->data);
     const uint64_t tbit = uint64_t(1) << target;
-    if (sizeof(T) == 4 && can_vec2(map, items0)) {
-        const uint64_t items = items0 / 2;
-        hipLaunchKernelGGL((k_diag<T, 2, kItems, NTV>), dim3(grid_for(items, kBlock * kItems)), dim3(kBlock), 0, s->stream, a, items,
-                           map, tbit, d[0], d[1], d[2], d[3], int(mode));
-    } else {
+    bool vec2 = false;  // complex64 only, as in general_t
+    if constexpr (sizeof(T) == 4) {
+        vec2 = can_vec2(map, items0);
+        if (vec2) {
+            const uint64_t items = items0 / 2;
+            hipLaunchKernelGGL((k_diag<T, 2, kItems, NTV>), dim3(grid_for(items, kBlock * kItems)), dim3(kBlock), 0, s->stream, a,
+                               items, map, tbit, d[0], d[1], d[2], d[3], int(mode));
+        }
+    }
+    if (!vec2) {
         hipLaunchKernelGGL((k_diag<T, 1, kItems, NTV>), dim3(grid_for(items0, kBlock * kItems)), dim3(kBlock), 0, s->stream, a,
                            items0, map, tbit, d[0], d[1], d[2], d[3], int(mode));
     }
@@ -472,11 +490,16 @@ int swap_nt(qsim_state *s, const IndexMap &map, uint64_t flip)
 {
     const uint64_t items0 = dim(s->n) >> map.npos;
     T *a = static_cast<T *>(s->data);
-    if (sizeof(T) == 4 && can_vec2(map, items0)) {
-        const uint64_t items = items0 / 2;
-        hipLaunchKernelGGL((k_swap<T, 2, kItems, NTV>), dim3(grid_for(items, kBlock * kItems)), dim3(kBlock), 0, s->stream, a, items,
-                           map, flip);
-    } else {
+    bool vec2 = false;  // complex64 only, as in general_t
+    if constexpr (sizeof(T) == 4) {
+        vec2 = can_vec2(map, items0);
+        if (vec2) {
+            const uint64_t items = items0 / 2;
+            hipLaunchKernelGGL((k_swap<T, 2, kItems, NTV>), dim3(grid_for(items, kBlock * kItems)), dim3(kBlock), 0, s->stream, a,
+                               items, map, flip);
+        }
+    }
+    if (!vec2) {
         hipLaunchKernelGGL((k_swap<T, 1, kItems, NTV>), dim3(grid_for(items0, kBlock * kItems)), dim3(kBlock), 0, s->stream, a,
                            items0, map, flip);
     }
