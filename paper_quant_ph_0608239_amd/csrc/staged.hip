@@ -16,6 +16,8 @@
 // block goes through LDS once to change RB. LDS slots are padded (one slot per 2^P) so that the
 // usual RB/TB splits are free of bank conflicts.
 #include <algorithm>
+#include <array>
+#include <cstring>
 #include <cmath>
 
 #include "qsim_internal.h"
@@ -146,40 +148,34 @@ inline void cmul_host(double &ar, double &ai, double br, double bi)
 // swap moves it to the other qubit, and X exchanges its two entries (X D = D' X). The next
 // uncontrolled dense gate on the qubit absorbs it as a column scaling (U_next D). Where a gate
 // that does not commute with it comes (a gate with controls that targets the qubit), or at the end
-// of the circuit, it is applied as a phase gate diag(1, e1/e0); the factors e0 of all of them form
-// one global phase, applied last. The circuit's unitary is unchanged; a 2x2 with a real first
-// column costs 12 multiply-adds per amplitude pair instead of 16.
+// of the circuit, D goes back into the gate that split it off: that gate keeps its unsplit matrix
+// (every gate between it and here commutes with D). The circuit's unitary is unchanged, no gate is
+// added, and a 2x2 with a real first column costs 12 multiply-adds per amplitude pair instead of 16.
 void carry_row_phases(int n, std::vector<GInfo> &g)
 {
     struct Ph {
         double r0 = 1.0, i0 = 0.0, r1 = 1.0, i1 = 0.0;
+        long src = -1;  // index in the output of the gate D was split off, -1: D = identity
     };
     std::vector<Ph> pend(static_cast<size_t>(n), Ph{});
-    double gr = 1.0, gim = 0.0;  // global phase
+    std::vector<std::array<double, 8>> unsplit;  // matrix of each output gate before the split
     std::vector<GInfo> out;
-    out.reserve(g.size() + size_t(n) + 1);
+    out.reserve(g.size());
+    unsplit.reserve(g.size());
+    auto emit = [&](const GInfo &x) {
+        out.push_back(x);
+        std::array<double, 8> m;
+        memcpy(m.data(), x.m, sizeof(x.m));
+        unsplit.push_back(m);
+    };
     auto flush = [&](int q) {
         Ph &p = pend[size_t(q)];
-        if (p.r0 == 1.0 && p.i0 == 0.0 && p.r1 == 1.0 && p.i1 == 0.0) return;
-        // diag(e0, e1) = e0 diag(1, e1 / e0), |e0| = 1
-        double fr = p.r1, fi = p.i1;
-        cmul_host(fr, fi, p.r0, -p.i0);
-        cmul_host(gr, gim, p.r0, p.i0);
-        if (!(fr == 1.0 && fi == 0.0)) {
-            GInfo d{};
-            d.kind = G_PHASE;
-            d.target = q;
-            d.target2 = -1;
-            d.qmask = uint64_t(1) << q;
-            d.m[0] = fr;
-            d.m[1] = fi;
-            out.push_back(d);
-        }
+        if (p.src >= 0) memcpy(out[size_t(p.src)].m, unsplit[size_t(p.src)].data(), sizeof(out[0].m));
         p = Ph{};
     };
     for (const GInfo &x : g) {
         if (diagonal(x)) {
-            out.push_back(x);
+            emit(x);
             continue;
         }
         if (x.kind == G_SWAP) {
@@ -189,20 +185,20 @@ void carry_row_phases(int n, std::vector<GInfo> &g)
                 flush(x.target);
                 flush(x.target2);
             }
-            out.push_back(x);
+            emit(x);
             continue;
         }
         const int q = x.target;
         Ph &p = pend[size_t(q)];
         if (x.controls != 0) {
             flush(q);
-            out.push_back(x);
+            emit(x);
             continue;
         }
         if (x.kind == G_X) {
             std::swap(p.r0, p.r1);
             std::swap(p.i0, p.i1);
-            out.push_back(x);
+            emit(x);
             continue;
         }
         GInfo y = x;
@@ -210,9 +206,11 @@ void carry_row_phases(int n, std::vector<GInfo> &g)
         cmul_host(y.m[4], y.m[5], p.r0, p.i0);
         cmul_host(y.m[2], y.m[3], p.r1, p.i1);  // column 1 times e1
         cmul_host(y.m[6], y.m[7], p.r1, p.i1);
+        emit(y);  // records the unsplit matrix U D
+        GInfo &z = out.back();
         Ph e;
         for (int k = 0; k < 2; ++k) {  // row k divided by the phase of its first entry
-            double &ar = y.m[4 * k], &ai = y.m[4 * k + 1];
+            double &ar = z.m[4 * k], &ai = z.m[4 * k + 1];
             const double a = std::hypot(ar, ai);
             double er = 1.0, ei = 0.0;
             if (a > 0.0) {
@@ -221,24 +219,15 @@ void carry_row_phases(int n, std::vector<GInfo> &g)
             }
             ar = a;
             ai = 0.0;
-            cmul_host(y.m[4 * k + 2], y.m[4 * k + 3], er, -ei);
+            cmul_host(z.m[4 * k + 2], z.m[4 * k + 3], er, -ei);
             (k == 0 ? e.r0 : e.r1) = er;
             (k == 0 ? e.i0 : e.i1) = ei;
         }
+        const bool trivial = e.r0 == 1.0 && e.i0 == 0.0 && e.r1 == 1.0 && e.i1 == 0.0;
+        e.src = trivial ? -1 : long(out.size() - 1);
         p = e;
-        out.push_back(y);
     }
     for (int q = 0; q < n; ++q) flush(q);
-    if (!(gr == 1.0 && gim == 0.0)) {
-        GInfo d{};
-        d.kind = G_DIAG;
-        d.target = 0;
-        d.target2 = -1;
-        d.qmask = 1;
-        d.m[0] = d.m[2] = gr;
-        d.m[1] = d.m[3] = gim;
-        out.push_back(d);
-    }
     g.swap(out);
 }
 

@@ -128,6 +128,10 @@ template <bool S> __device__ __forceinline__ void fma_into(float &x, float c, fl
     else asm("v_fma_f32 %0, %1, %0, %2" : "+v"(x) : "v"(c), "v"(t));
 }
 
+// fused multiply-add in the type's own precision (__builtin_fma is the double one)
+__device__ __forceinline__ double fmat(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float fmat(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+
 // x <- (fr + i fi) x
 template <typename T>
 __device__ __forceinline__ void cmul(typename Vec<T>::C &x, T fr, T fi)
@@ -150,14 +154,14 @@ __device__ __forceinline__ void pair2x2(typename Vec<T>::C &a, typename Vec<T>::
     T t1 = u.i[0] * a.x;
     T t2 = u.r[2] * a.x;
     T t3 = u.r[2] * a.y;
-    t0 = __builtin_fma(-u.i[1], b.y, t0);
-    t1 = __builtin_fma(u.r[1], b.y, t1);
-    t2 = __builtin_fma(-u.i[2], a.y, t2);
-    t3 = __builtin_fma(u.i[2], a.x, t3);
-    t0 = __builtin_fma(-u.i[0], a.y, t0);
-    t1 = __builtin_fma(u.i[1], b.x, t1);
-    t2 = __builtin_fma(-u.i[3], b.y, t2);
-    t3 = __builtin_fma(u.i[3], b.x, t3);
+    t0 = fmat(-u.i[1], b.y, t0);
+    t1 = fmat(u.r[1], b.y, t1);
+    t2 = fmat(-u.i[2], a.y, t2);
+    t3 = fmat(u.i[2], a.x, t3);
+    t0 = fmat(-u.i[0], a.y, t0);
+    t1 = fmat(u.i[1], b.x, t1);
+    t2 = fmat(-u.i[3], b.y, t2);
+    t3 = fmat(u.i[3], b.x, t3);
     fma_into<S>(a.x, u.r[0], t0);
     fma_into<S>(a.y, u.r[0], t1);
     fma_into<S>(b.x, u.r[3], t2);
@@ -173,10 +177,10 @@ __device__ __forceinline__ void pair2x2_rc(typename Vec<T>::C &a, typename Vec<T
     T s3 = u.r[2] * a.y;
     T s0 = u.r[1] * b.x;
     T s1 = u.r[1] * b.y;
-    s2 = __builtin_fma(-u.i[3], b.y, s2);
-    s3 = __builtin_fma(u.i[3], b.x, s3);
-    s0 = __builtin_fma(-u.i[1], b.y, s0);
-    s1 = __builtin_fma(u.i[1], b.x, s1);
+    s2 = fmat(-u.i[3], b.y, s2);
+    s3 = fmat(u.i[3], b.x, s3);
+    s0 = fmat(-u.i[1], b.y, s0);
+    s1 = fmat(u.i[1], b.x, s1);
     fma_into<S>(a.x, u.r[0], s0);
     fma_into<S>(a.y, u.r[0], s1);
     fma_into<S>(b.x, u.r[3], s2);
@@ -203,8 +207,18 @@ __device__ __forceinline__ void op_dense_all(typename Vec<T>::C *x, const SOp &o
         if (!((r >> RB) & 1)) pair2x2_rc<T, true>(x[r], x[r | (1 << RB)], u);
 }
 
-// A dense op with a fused flip chosen per pair (register bits) or per block: pairs that take it use
-// the 2x2 with row 1 (or column 1) negated; the choice is made on scalar registers.
+// sign toggle by an integer xor of the sign bit (exact); t is 0 or 0x80000000
+__device__ __forceinline__ void xor_sign(double &v, uint32_t t)
+{
+    uint2 w = __builtin_bit_cast(uint2, v);
+    w.y ^= t;
+    v = __builtin_bit_cast(double, w);
+}
+__device__ __forceinline__ void xor_sign(float &v, uint32_t t) { v = __builtin_bit_cast(float, __builtin_bit_cast(uint32_t, v) ^ t); }
+
+// A dense op with a fused flip chosen per pair (register bits) or per block: in the pairs that take
+// it, the second amplitude changes sign before the 2x2 (column flip) or after it (row flip). The
+// per-pair sign words are wave-uniform.
 template <typename T, int E, int RB>
 __device__ __forceinline__ void op_dense_alt_uniform(typename Vec<T>::C *x, const SOp &op, uint64_t base)
 {
@@ -215,21 +229,19 @@ __device__ __forceinline__ void op_dense_alt_uniform(typename Vec<T>::C *x, cons
         u.r[k] = c[2 * k];
         u.i[k] = c[2 * k + 1];
     }
-    const bool blk = (base & op.galt) == op.galt;
-    const int off = op.alt_col ? 1 : 2;  // the entry negated besides u11: u01 (column) or u10 (row)
+    const uint32_t am = (base & op.galt) == op.galt ? op.amask : 0u;
+    const uint32_t col = op.alt_col ? 0x80000000u : 0u, row = op.alt_col ? 0u : 0x80000000u;
 #pragma unroll
     for (int r = 0; r < E; ++r) {
         if ((r >> RB) & 1) continue;
         const int p = (r & ((1 << RB) - 1)) | ((r >> (RB + 1)) << RB);
-        const bool neg = blk && ((op.amask >> p) & 1);
-        U2<T> w = u;
-        w.r[1] = (neg && off == 1) ? -u.r[1] : u.r[1];
-        w.i[1] = (neg && off == 1) ? -u.i[1] : u.i[1];
-        w.r[2] = (neg && off == 2) ? -u.r[2] : u.r[2];
-        w.i[2] = (neg && off == 2) ? -u.i[2] : u.i[2];
-        w.r[3] = neg ? -u.r[3] : u.r[3];
-        w.i[3] = neg ? -u.i[3] : u.i[3];
-        pair2x2_rc<T, true>(x[r], x[r | (1 << RB)], w);
+        const bool neg = (am >> p) & 1;
+        const uint32_t tc = neg ? col : 0u, tr = neg ? row : 0u;
+        xor_sign(x[r | (1 << RB)].x, tc);
+        xor_sign(x[r | (1 << RB)].y, tc);
+        pair2x2_rc<T, true>(x[r], x[r | (1 << RB)], u);
+        xor_sign(x[r | (1 << RB)].x, tr);
+        xor_sign(x[r | (1 << RB)].y, tr);
     }
 }
 
