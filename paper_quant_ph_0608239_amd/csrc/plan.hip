@@ -445,6 +445,8 @@ int qsim_plan_tune(int n, int dtype, const qsim_gate *gates, int64_t ngates, qsi
     if (include_plain) cand.push_back(qsim_plan_opts{QSIM_PLAN_PLAIN, 0, 0, 0, 0});
     for (int k = 2; k <= 5; ++k) cand.push_back(qsim_plan_opts{QSIM_PLAN_FUSED, k, 0, 0, 0});
     // (resident qubits, log2 amplitudes per thread) of the compiled LDS-staged variants
+    // (13 resident qubits for complex128 and 14 for complex64 leave room for one workgroup per CU;
+    // they measured slower than two smaller ones on the brickwork and are not candidates)
     static const int v128[][2] = {{12, 4}, {11, 4}, {10, 4}, {12, 3}, {11, 3}, {10, 3}};
     static const int v64[][2] = {{12, 4}, {11, 4}, {13, 4}, {13, 5}, {12, 5}, {11, 5}};
     for (const auto &v : dtype == QSIM_C128 ? v128 : v64)

@@ -236,9 +236,9 @@ void carry_row_phases(int n, std::vector<GInfo> &g)
 // kernel variants: (amplitudes per thread, threads) per dtype; see launch_pass
 bool staged::staged_variant_ok(int dtype, int log_e, int log_t)
 {
-    if (log_t < 6 || log_t > 9) return false;
-    if (dtype == QSIM_C128) return (log_e == 3 && log_t >= 7) || (log_e == 4 && log_t <= 8);
-    return (log_e == 4 && log_t >= 7) || (log_e == 5 && log_t <= 8);
+    if (log_t < 6 || log_t > 10) return false;
+    if (dtype == QSIM_C128) return (log_e == 3 && log_t >= 7 && log_t <= 9) || (log_e == 4 && log_t <= 9);
+    return (log_e == 4 && log_t >= 7) || (log_e == 5 && log_t <= 9);
 }
 
 namespace {
@@ -272,8 +272,9 @@ bool commute(const HOp &a, const HOp &b)
 // element masks) and its thread part, and order the ops into rounds. An op goes to the earliest
 // round in which it runs after every earlier op of the stage it does not commute with (within a
 // round: bit 0 ops, ..., bit LOG_E-1 ops, unconditional before conditional, then diagonal ops).
-static void emit_stage(SStage cur, uint32_t rbset, int log_e, int m, const int *localof, const std::vector<HOp> &sops,
-                       std::vector<SStage> &stages, std::vector<SRound> &rounds, std::vector<SOp> &ops)
+static void emit_stage(SStage cur, uint32_t rbset, int log_e, int m, int dtype, const int *localof, const uint8_t *R,
+                       const std::vector<HOp> &sops, std::vector<SStage> &stages, std::vector<SRound> &rounds,
+                       std::vector<SOp> &ops)
 {
     const int E = 1 << log_e;
     int nrb = __builtin_popcount(rbset);
@@ -283,10 +284,29 @@ static void emit_stage(SStage cur, uint32_t rbset, int log_e, int m, const int *
             rbset |= 1u << s;
             ++nrb;
         }
-    for (int s = 0, j = 0, jt = 0; s < m; ++s) {
+    for (int s = 0, j = 0; s < m; ++s)
         if ((rbset >> s) & 1) cur.rb[j++] = uint8_t(s);
-        else cur.tbits[jt++] = uint8_t(s);
+    // Thread bits, lowest lane first. LDS slot s(e) = e + (e >> P) (one pad slot per 2^P) puts a
+    // lane bit at local position b < 2P on the bank group of b mod P (and higher positions on none),
+    // so the first P lanes take one position from each residue class where the register bits leave
+    // one: then the 2^P lanes of a wide LDS access hit distinct bank groups. The low run keeps its
+    // order (0, 1, ... are their own classes), so stages that read memory directly stay coalesced.
+    {
+        const int P = dtype == QSIM_C128 ? 4 : 5;
+        uint32_t left = ((1u << m) - 1) & ~rbset;
+        int jt = 0;
+        for (int c = 0; c < P && jt < m - log_e; ++c)
+            for (int b = c; b < 2 * P && b < m; b += P)
+                if ((left >> b) & 1) {
+                    cur.tbits[jt++] = uint8_t(b);
+                    left &= ~(1u << b);
+                    break;
+                }
+        for (int b = 0; b < m; ++b)
+            if ((left >> b) & 1) cur.tbits[jt++] = uint8_t(b);
     }
+    for (int j = 0; j < log_e; ++j) cur.prb[j] = R[cur.rb[j]];
+    for (int j = 0; j < m - log_e; ++j) cur.ptb[j] = R[cur.tbits[j]];
     auto rank_of = [&](int lb) { return __builtin_popcount(rbset & ((1u << lb) - 1)); };
     const size_t N = sops.size();
     std::vector<SOp> rec(N);
@@ -515,7 +535,7 @@ int staged::staged_schedule(int n, int dtype, int m, int log_e, const std::vecto
         uint32_t rbset = 0;
         int nrb = 0;
         auto close_stage = [&]() {
-            emit_stage(cur, rbset, log_e, m, localof, sops, stages, rounds, ops);
+            emit_stage(cur, rbset, log_e, m, dtype, localof, ps.R, sops, stages, rounds, ops);
             sops.clear();
             cur = SStage{};
             cur.swap_p = cur.swap_q = -1;
@@ -657,6 +677,7 @@ static int launch_pass(StagedPlan *p, qsim_state *s, size_t i)
         case 3 * 16 + 9: launch_variant<double, 3, 9, 3>(p, s, i); break;
         case 4 * 16 + 6: launch_variant<double, 4, 6, 2>(p, s, i); break;
         case 4 * 16 + 7: launch_variant<double, 4, 7, 2>(p, s, i); break;
+        case 4 * 16 + 9: launch_variant<double, 4, 9, 2>(p, s, i); break;  // 13 resident qubits, one workgroup per CU
         default: launch_variant<double, 4, 8, 2>(p, s, i); break;
         }
     } else {
@@ -666,6 +687,8 @@ static int launch_pass(StagedPlan *p, qsim_state *s, size_t i)
         case 4 * 16 + 9: launch_variant<float, 4, 9, 2>(p, s, i); break;
         case 5 * 16 + 6: launch_variant<float, 5, 6, 1>(p, s, i); break;
         case 5 * 16 + 7: launch_variant<float, 5, 7, 1>(p, s, i); break;
+        case 5 * 16 + 9: launch_variant<float, 5, 9, 1>(p, s, i); break;   // 14 resident qubits, one workgroup per CU
+        case 4 * 16 + 10: launch_variant<float, 4, 10, 4>(p, s, i); break; // 14 resident qubits, 1024 threads
         default: launch_variant<float, 5, 8, 1>(p, s, i); break;
         }
     }

@@ -50,12 +50,14 @@ struct SRound {
 struct SStage {
     int32_t round_begin, round_end;
     uint8_t rb[8];      // register bits (local bit indices), LOG_E of them, ascending
-    uint8_t tbits[8];   // thread bits (the other local bits), LOG_T of them, ascending
+    uint8_t tbits[8];   // thread bits (the other local bits), LOG_T of them, lowest lane first
     int32_t swap_p;     // stage-end local swap (quantum swap of two resident qubits), -1 if none
     int32_t swap_q;
     uint32_t swap_lcm;  // its local condition
     uint32_t pad;
     uint64_t swap_gcm;  // its condition on non-resident bits
+    uint8_t prb[8];     // index bit (physical qubit) of each register bit
+    uint8_t ptb[8];     // index bit of each thread bit, lowest lane first
 };
 
 struct SPass {
@@ -443,7 +445,7 @@ __device__ __forceinline__ void run_stages(T *__restrict__ a, const SPass &pass,
     C x[E];
     for (int si = pass.stage_begin; si < pass.stage_end; ++si) {
         const SStage st = ldc<SStage>(stages + si);
-        // thread bits: the local bits that are not register bits, in ascending order
+        // thread bits: the local bits that are not register bits, in the stage's lane order
         uint32_t et = 0;
 #pragma unroll
         for (int j = 0; j < LOG_T; ++j) et |= uint32_t((t >> j) & 1) << st.tbits[j];
@@ -464,14 +466,14 @@ __device__ __forceinline__ void run_stages(T *__restrict__ a, const SPass &pass,
         if (in_mem) {
 #pragma unroll
             for (int j = 0; j < LOG_T; ++j)
-                if ((t >> j) & 1) gt |= uint64_t(1) << pass.R[st.tbits[j]];
+                if ((t >> j) & 1) gt |= uint64_t(1) << st.ptb[j];
             gt |= base;
         }
         auto gr = [&](int r) {  // uniform
             uint64_t v = 0;
 #pragma unroll
             for (int j = 0; j < LOG_E; ++j)
-                if ((r >> j) & 1) v |= uint64_t(1) << pass.R[st.rb[j]];
+                if ((r >> j) & 1) v |= uint64_t(1) << st.prb[j];
             return v;
         };
         if (in_mem) {
@@ -531,14 +533,14 @@ __device__ __forceinline__ void run_stages(T *__restrict__ a, const SPass &pass,
         uint64_t gt = base;
 #pragma unroll
         for (int j = 0; j < LOG_T; ++j)
-            if ((t >> j) & 1) gt |= uint64_t(1) << pass.R[st.tbits[j]];
+            if ((t >> j) & 1) gt |= uint64_t(1) << st.ptb[j];
         C *agw = reinterpret_cast<C *>(a) + gt;
 #pragma unroll
         for (int r = 0; r < E; ++r) {
             uint64_t v = 0;
 #pragma unroll
             for (int j = 0; j < LOG_E; ++j)
-                if ((r >> j) & 1) v |= uint64_t(1) << pass.R[st.rb[j]];
+                if ((r >> j) & 1) v |= uint64_t(1) << st.prb[j];
             st_nt(agw + v, x[r]);
         }
     }
