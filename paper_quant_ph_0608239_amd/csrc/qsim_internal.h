@@ -60,6 +60,7 @@ struct IndexMap {
     uint64_t posmask;   // positions of the inserted zero bits
     int32_t npos;       // number of inserted zero bits (popcount of posmask)
     int32_t p0;         // lowest inserted position (64 if none)
+    uint64_t lo[3];     // npos <= 3: 2^p - 1 for the inserted positions p, ascending; all ones past npos
 };
 
 IndexMap make_index_map(uint64_t posmask, uint64_t set);
@@ -73,6 +74,18 @@ __device__ __forceinline__ uint64_t insert_zeros(uint64_t j, const IndexMap &m)
         const int p = __builtin_ctzll(pm);
         pm &= pm - 1;
         const uint64_t lo = j & ((uint64_t(1) << p) - 1);
+        j = lo | ((j ^ lo) << 1);
+    }
+    return j | m.set;
+}
+
+// The same for m.npos <= 3 (a target with up to two controls) in three fixed steps, without a loop
+// (an all-ones mask leaves j unchanged)
+__device__ __forceinline__ uint64_t insert_zeros3(uint64_t j, const IndexMap &m)
+{
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const uint64_t lo = j & m.lo[k];
         j = lo | ((j ^ lo) << 1);
     }
     return j | m.set;

@@ -86,9 +86,28 @@ __device__ __forceinline__ void cmul(T &xr, T &xi, T fr, T fi)
     xi = i;
 }
 
+// Sweep bodies come in two forms. FAST: every chunk of kBlock * ITEMS items is full and at most three
+// bits are inserted, so the items need no range checks and their indices come from fixed steps; the
+// loads of all items issue back to back. Otherwise every item is range-checked and its index is
+// built by the general walk.
+template <bool FAST> __device__ __forceinline__ uint64_t index_of(uint64_t j, const IndexMap &m)
+{
+    if constexpr (FAST) return insert_zeros3(j, m);
+    else return insert_zeros(j, m);
+}
+template <bool FAST> __device__ __forceinline__ bool in_range(uint64_t j, uint64_t items)
+{
+    if constexpr (FAST) return true;
+    else return j < items;
+}
+template <int ITEMS> __device__ __forceinline__ bool fast_form(uint64_t items, const IndexMap &m)
+{
+    return m.npos <= 3 && items % (uint64_t(kBlock) * ITEMS) == 0;
+}
+
 // ---- general 2x2 on pairs ----------------------------------------------------------------------
-template <typename T, int VEC, int ITEMS, bool NT>
-__global__ __launch_bounds__(kBlock) void k_general(T *__restrict__ a, uint64_t items, IndexMap map, uint64_t tbit,
+template <typename T, int VEC, int ITEMS, bool NT, bool FAST>
+__device__ __forceinline__ void k_general_body(T *__restrict__ a, uint64_t items, IndexMap map, uint64_t tbit,
                                                    Mat2 um)
 {
     using C = typename Vec<T>::C;
@@ -102,8 +121,8 @@ __global__ __launch_bounds__(kBlock) void k_general(T *__restrict__ a, uint64_t 
 #pragma unroll
         for (int k = 0; k < ITEMS; ++k) {
             const uint64_t j = base + uint64_t(k) * kBlock;
-            if (j < items) {
-                i0[k] = insert_zeros(j * VEC, map);
+            if (in_range<FAST>(j, items)) {
+                i0[k] = index_of<FAST>(j * VEC, map);
                 if constexpr (VEC == 2) {
                     const C2 p = ldw<NT, C2>(a + 2 * i0[k]);
                     const C2 q = ldw<NT, C2>(a + 2 * (i0[k] | tbit));
@@ -120,7 +139,7 @@ __global__ __launch_bounds__(kBlock) void k_general(T *__restrict__ a, uint64_t 
 #pragma unroll
         for (int k = 0; k < ITEMS; ++k) {
             const uint64_t j = base + uint64_t(k) * kBlock;
-            if (j < items) {
+            if (in_range<FAST>(j, items)) {
 #pragma unroll
                 for (int v = 0; v < VEC; ++v) mix(u, x0[k][v], x1[k][v]);
                 if constexpr (VEC == 2) {
@@ -133,6 +152,14 @@ __global__ __launch_bounds__(kBlock) void k_general(T *__restrict__ a, uint64_t 
             }
         }
     }
+}
+
+template <typename T, int VEC, int ITEMS, bool NT>
+__global__ __launch_bounds__(kBlock) void k_general(T *__restrict__ a, uint64_t items, IndexMap map, uint64_t tbit,
+                                                   Mat2 um)
+{
+    if (fast_form<ITEMS>(items, map)) k_general_body<T, VEC, ITEMS, NT, true>(a, items, map, tbit, um);
+    else k_general_body<T, VEC, ITEMS, NT, false>(a, items, map, tbit, um);
 }
 
 
@@ -211,8 +238,8 @@ __global__ __launch_bounds__(kBlock) void k_general_wave(T *__restrict__ a, uint
 }
 
 // ---- one phase factor on the selected amplitudes ---------------------------------------------
-template <typename T, int VEC, int ITEMS, bool NT>
-__global__ __launch_bounds__(kBlock) void k_phase(T *__restrict__ a, uint64_t items, IndexMap map, double c0, double c1,
+template <typename T, int VEC, int ITEMS, bool NT, bool FAST>
+__device__ __forceinline__ void k_phase_body(T *__restrict__ a, uint64_t items, IndexMap map, double c0, double c1,
                                                  int angle_mode)
 {
     using C = typename Vec<T>::C;
@@ -227,8 +254,8 @@ __global__ __launch_bounds__(kBlock) void k_phase(T *__restrict__ a, uint64_t it
 #pragma unroll
         for (int k = 0; k < ITEMS; ++k) {
             const uint64_t j = base + uint64_t(k) * kBlock;
-            if (j < items) {
-                idx[k] = insert_zeros(j * VEC, map);
+            if (in_range<FAST>(j, items)) {
+                idx[k] = index_of<FAST>(j * VEC, map);
                 if constexpr (VEC == 2) {
                     const C2 p = ldw<NT, C2>(a + 2 * idx[k]);
                     x[k][0] = C{p.x, p.y};
@@ -241,7 +268,7 @@ __global__ __launch_bounds__(kBlock) void k_phase(T *__restrict__ a, uint64_t it
 #pragma unroll
         for (int k = 0; k < ITEMS; ++k) {
             const uint64_t j = base + uint64_t(k) * kBlock;
-            if (j < items) {
+            if (in_range<FAST>(j, items)) {
 #pragma unroll
                 for (int v = 0; v < VEC; ++v) cmul(x[k][v].x, x[k][v].y, fr, fi);
                 if constexpr (VEC == 2)
@@ -253,9 +280,17 @@ __global__ __launch_bounds__(kBlock) void k_phase(T *__restrict__ a, uint64_t it
     }
 }
 
-// ---- diag(d0, d1) on the target, controlled ----------------------------------------------------
 template <typename T, int VEC, int ITEMS, bool NT>
-__global__ __launch_bounds__(kBlock) void k_diag(T *__restrict__ a, uint64_t items, IndexMap map, uint64_t tbit,
+__global__ __launch_bounds__(kBlock) void k_phase(T *__restrict__ a, uint64_t items, IndexMap map, double c0, double c1,
+                                                 int angle_mode)
+{
+    if (fast_form<ITEMS>(items, map)) k_phase_body<T, VEC, ITEMS, NT, true>(a, items, map, c0, c1, angle_mode);
+    else k_phase_body<T, VEC, ITEMS, NT, false>(a, items, map, c0, c1, angle_mode);
+}
+
+// ---- diag(d0, d1) on the target, controlled ----------------------------------------------------
+template <typename T, int VEC, int ITEMS, bool NT, bool FAST>
+__device__ __forceinline__ void k_diag_body(T *__restrict__ a, uint64_t items, IndexMap map, uint64_t tbit,
                                                 double d0r, double d0i, double d1r, double d1i, int angle_mode)
 {
     using C = typename Vec<T>::C;
@@ -273,8 +308,8 @@ __global__ __launch_bounds__(kBlock) void k_diag(T *__restrict__ a, uint64_t ite
 #pragma unroll
         for (int k = 0; k < ITEMS; ++k) {
             const uint64_t j = base + uint64_t(k) * kBlock;
-            if (j < items) {
-                idx[k] = insert_zeros(j * VEC, map);
+            if (in_range<FAST>(j, items)) {
+                idx[k] = index_of<FAST>(j * VEC, map);
                 if constexpr (VEC == 2) {
                     const C2 p = ldw<NT, C2>(a + 2 * idx[k]);
                     x[k][0] = C{p.x, p.y};
@@ -287,7 +322,7 @@ __global__ __launch_bounds__(kBlock) void k_diag(T *__restrict__ a, uint64_t ite
 #pragma unroll
         for (int k = 0; k < ITEMS; ++k) {
             const uint64_t j = base + uint64_t(k) * kBlock;
-            if (j < items) {
+            if (in_range<FAST>(j, items)) {
 #pragma unroll
                 for (int v = 0; v < VEC; ++v) {
                     const bool one = ((idx[k] + v) & tbit) != 0;
@@ -302,9 +337,17 @@ __global__ __launch_bounds__(kBlock) void k_diag(T *__restrict__ a, uint64_t ite
     }
 }
 
-// ---- permutation: swap a(i) <-> a(i ^ flip), no arithmetic (bit-exact) -------------------------
 template <typename T, int VEC, int ITEMS, bool NT>
-__global__ __launch_bounds__(kBlock) void k_swap(T *__restrict__ a, uint64_t items, IndexMap map, uint64_t flip)
+__global__ __launch_bounds__(kBlock) void k_diag(T *__restrict__ a, uint64_t items, IndexMap map, uint64_t tbit,
+                                                double d0r, double d0i, double d1r, double d1i, int angle_mode)
+{
+    if (fast_form<ITEMS>(items, map)) k_diag_body<T, VEC, ITEMS, NT, true>(a, items, map, tbit, d0r, d0i, d1r, d1i, angle_mode);
+    else k_diag_body<T, VEC, ITEMS, NT, false>(a, items, map, tbit, d0r, d0i, d1r, d1i, angle_mode);
+}
+
+// ---- permutation: swap a(i) <-> a(i ^ flip), no arithmetic (bit-exact) -------------------------
+template <typename T, int VEC, int ITEMS, bool NT, bool FAST>
+__device__ __forceinline__ void k_swap_body(T *__restrict__ a, uint64_t items, IndexMap map, uint64_t flip)
 {
     // moved as raw 8/16-byte words: no floating-point operation touches the data
     using W = typename std::conditional<sizeof(T) * 2 * VEC == 16, uint4, uint2>::type;
@@ -315,8 +358,8 @@ __global__ __launch_bounds__(kBlock) void k_swap(T *__restrict__ a, uint64_t ite
 #pragma unroll
         for (int k = 0; k < ITEMS; ++k) {
             const uint64_t j = base + uint64_t(k) * kBlock;
-            if (j < items) {
-                i0[k] = insert_zeros(j * VEC, map);
+            if (in_range<FAST>(j, items)) {
+                i0[k] = index_of<FAST>(j * VEC, map);
                 x0[k] = ldw<NT, W>(a + 2 * i0[k]);
                 x1[k] = ldw<NT, W>(a + 2 * (i0[k] ^ flip));
             }
@@ -324,12 +367,19 @@ __global__ __launch_bounds__(kBlock) void k_swap(T *__restrict__ a, uint64_t ite
 #pragma unroll
         for (int k = 0; k < ITEMS; ++k) {
             const uint64_t j = base + uint64_t(k) * kBlock;
-            if (j < items) {
+            if (in_range<FAST>(j, items)) {
                 stw<NT>(a + 2 * i0[k], x1[k]);
                 stw<NT>(a + 2 * (i0[k] ^ flip), x0[k]);
             }
         }
     }
+}
+
+template <typename T, int VEC, int ITEMS, bool NT>
+__global__ __launch_bounds__(kBlock) void k_swap(T *__restrict__ a, uint64_t items, IndexMap map, uint64_t flip)
+{
+    if (fast_form<ITEMS>(items, map)) k_swap_body<T, VEC, ITEMS, NT, true>(a, items, map, flip);
+    else k_swap_body<T, VEC, ITEMS, NT, false>(a, items, map, flip);
 }
 
 template <typename T>
@@ -536,6 +586,15 @@ IndexMap make_index_map(uint64_t posmask, uint64_t set)
     m.posmask = posmask;
     m.npos = __builtin_popcountll(posmask);
     m.p0 = posmask ? __builtin_ctzll(posmask) : 64;
+    uint64_t pm = posmask;
+    for (int k = 0; k < 3; ++k) {
+        if (pm) {
+            m.lo[k] = (uint64_t(1) << __builtin_ctzll(pm)) - 1;
+            pm &= pm - 1;
+        } else {
+            m.lo[k] = ~uint64_t(0);
+        }
+    }
     return m;
 }
 
