@@ -312,7 +312,7 @@ def main() -> int:
     ap.add_argument("--lds-regs", type=int, default=0, help="log2 amplitudes per thread (staged plans)")
     ap.add_argument("--plain-runs", type=int, default=1, help="timed runs of the plain per-gate plan (0 = skip)")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
-    ap.add_argument("--cpu-n", type=int, default=26)
+    ap.add_argument("--cpu-n", type=int, default=27)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--renorm-every", type=int, default=None,
                     help="layers between FP64 renormalisations (default 10 for complex64, 0 = none for complex128)")

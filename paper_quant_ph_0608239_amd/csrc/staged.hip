@@ -464,6 +464,8 @@ int staged::staged_schedule(int n, int dtype, int m, int log_e, const std::vecto
                             std::vector<SPass> &passes, std::vector<SStage> &stages, std::vector<SRound> &rounds,
                             std::vector<SOp> &ops)
 {
+    if (m > kMaxM || log_e < 1 || log_e > kMaxLogE || m - log_e > kMaxLogT || m - log_e < 0)
+        return set_error(QSIM_EINVAL, "staged: block shape outside the kernel tables");
     const int L = dtype == QSIM_C128 ? 4 : 5;  // low run: 2^L amplitudes = 256 bytes
     std::vector<GInfo> gi(gates.size());
     for (size_t i = 0; i < gates.size(); ++i) gi[i] = describe(gates[i]);

@@ -10,6 +10,7 @@ namespace staged {
 
 constexpr int kMaxM = 14;
 constexpr int kMaxLogE = 5;
+constexpr int kMaxLogT = 10;  // threads per workgroup: at most 2^10
 
 // One operation of a stage. Dense ops act on one register bit (the list they sit in says which);
 // diagonal ops multiply register elements by per-lane factors.
@@ -49,16 +50,17 @@ struct SRound {
 
 struct SStage {
     int32_t round_begin, round_end;
-    uint8_t rb[8];      // register bits (local bit indices), LOG_E of them, ascending
-    uint8_t tbits[8];   // thread bits (the other local bits), LOG_T of them, lowest lane first
-    int32_t swap_p;     // stage-end local swap (quantum swap of two resident qubits), -1 if none
+    uint8_t rb[8];                // register bits (local bit indices), LOG_E of them, ascending
+    uint8_t tbits[kMaxLogT + 6];  // thread bits (the other local bits), LOG_T of them, lowest lane first
+    int32_t swap_p;               // stage-end local swap (quantum swap of two resident qubits), -1 if none
     int32_t swap_q;
-    uint32_t swap_lcm;  // its local condition
+    uint32_t swap_lcm;            // its local condition
     uint32_t pad;
-    uint64_t swap_gcm;  // its condition on non-resident bits
-    uint8_t prb[8];     // index bit (physical qubit) of each register bit
-    uint8_t ptb[8];     // index bit of each thread bit, lowest lane first
+    uint64_t swap_gcm;            // its condition on non-resident bits
+    uint8_t prb[8];               // index bit (physical qubit) of each register bit
+    uint8_t ptb[kMaxLogT + 6];    // index bit of each thread bit, lowest lane first
 };
+static_assert(sizeof(SStage) == 80, "stage record layout");
 
 struct SPass {
     int32_t m;
@@ -110,7 +112,8 @@ template <typename C> __device__ __forceinline__ void st_nt(C *p, const C &c)
 }
 
 // LDS slot of local index e: one padding slot per 2^P slots (P = 4 for 16-byte, 5 for 8-byte
-// amplitudes, i.e. one per 256 bytes)
+// amplitudes, i.e. one per 256 bytes). Additive over index parts without common bits:
+// slot(a | b) = slot(a) + slot(b).
 template <typename T> __device__ __forceinline__ int slot(int e) { return sizeof(T) == 8 ? e + (e >> 4) : e + (e >> 5); }
 template <typename T> __host__ __device__ constexpr int lds_slots(int m) { return (1 << m) + ((1 << m) >> (sizeof(T) == 8 ? 4 : 5)); }
 

@@ -347,6 +347,27 @@ def test_staged_brickwork(q, oracle_mod, dtype, lds):
     compare_circuit(s.download().astype(np.complex128), ref, dtype, f"staged lds={lds}")
 
 
+# every kernel variant (resident qubits m, 2^le amplitudes per thread): up to 2^10 threads per
+# workgroup, so the stage records carry up to 10 thread bits
+STAGED_VARIANTS = [("c128", m, le) for m, le in ((10, 3), (11, 3), (12, 3), (10, 4), (11, 4), (12, 4), (13, 4))] + \
+                  [("c64", m, le) for m, le in ((11, 4), (12, 4), (13, 4), (14, 4), (11, 5), (12, 5), (13, 5), (14, 5))]
+
+
+@pytest.mark.parametrize("dtype,m,le", STAGED_VARIANTS)
+def test_staged_every_variant(q, oracle_mod, dtype, m, le):
+    n = 16
+    for text in (wl.brickwork_circuit(n, 6, seed=29), wl.config0_circuit(n, 80, seed=5)):
+        ref = oracle_mod.run_circuit(text)
+        c = q.parse_circuit(text)
+        s = q.State(c.n, dtype)
+        p = q.Plan(c, dtype, method="staged", lds_qubits=m, lds_regs=le)
+        assert p.info["lds_qubits"] == m and p.info["lds_regs"] == le
+        p.execute(s)
+        compare_circuit(s.download().astype(np.complex128), ref, dtype, f"staged m={m} le={le}")
+        p.close()
+        s.close()
+
+
 @pytest.mark.parametrize("dtype", DTYPES)
 @pytest.mark.parametrize("seed", [1, 2])
 def test_staged_config0(q, oracle_mod, dtype, seed):
