@@ -16,6 +16,7 @@
 // block goes through LDS once to change RB. LDS slots are padded (one slot per 2^P) so that the
 // usual RB/TB splits are free of bank conflicts.
 #include <algorithm>
+#include <utility>
 #include <array>
 #include <cstring>
 #include <cmath>
@@ -474,8 +475,36 @@ int staged::staged_schedule(int n, int dtype, int m, int log_e, const std::vecto
     std::vector<char> done(G, 0);
     size_t ndone = 0;
 
+    // gates that a pass with resident set R executes, in circuit order: a gate runs when none of its
+    // qubits is held back by an earlier gate that does not run, and it is diagonal or its target(s)
+    // are resident
+    auto executable = [&](uint64_t R, std::vector<size_t> *take) {
+        int dense = 0, all = 0;
+        uint64_t blocked = 0;
+        for (size_t i = 0; i < G; ++i) {
+            if (done[i]) continue;
+            const GInfo &g = gi[i];
+            if (g.qmask & blocked) {
+                blocked |= g.qmask;
+                continue;
+            }
+            bool ok = diagonal(g) || ((R >> g.target) & 1);
+            if (g.kind == G_SWAP) ok = ((R >> g.target) & 1) && ((R >> g.target2) & 1);
+            if (ok) {
+                ++all;
+                if (!diagonal(g)) ++dense;
+                if (take) take->push_back(i);
+            } else {
+                blocked |= g.qmask;
+            }
+        }
+        return std::make_pair(dense, all);
+    };
     while (ndone < G) {
-        // --- resident set: the low run, then the targets of the earliest pending non-diagonal gates
+        // --- resident set. Candidates: the low run plus the targets of the earliest pending
+        // non-diagonal gates, and the low run plus every window of m - L consecutive qubits above it
+        // (a window lets a pass run the light cone of neighbouring-qubit circuits several layers
+        // deep). The pass takes the candidate that executes the most non-diagonal gates.
         uint64_t R = (uint64_t(1) << L) - 1;
         int cnt = L;
         for (size_t i = 0; i < G && cnt < m; ++i) {
@@ -497,6 +526,18 @@ int staged::staged_schedule(int n, int dtype, int m, int log_e, const std::vecto
                 R |= uint64_t(1) << q;
                 ++cnt;
             }
+        {
+            std::pair<int, int> best = executable(R, nullptr);
+            const int w = m - L;
+            for (int a = L; a + w <= n; ++a) {
+                const uint64_t Rw = ((uint64_t(1) << L) - 1) | (((uint64_t(1) << w) - 1) << a);
+                const std::pair<int, int> c = executable(Rw, nullptr);
+                if (c.first > best.first || (c.first == best.first && c.second > best.second)) {
+                    best = c;
+                    R = Rw;
+                }
+            }
+        }
         SPass ps{};
         ps.m = m;
         int localof[64];
@@ -515,19 +556,7 @@ int staged::staged_schedule(int n, int dtype, int m, int log_e, const std::vecto
         };
         // --- executable gates, in circuit order
         std::vector<size_t> take;
-        uint64_t blocked = 0;
-        for (size_t i = 0; i < G; ++i) {
-            if (done[i]) continue;
-            const GInfo &g = gi[i];
-            if (g.qmask & blocked) {
-                blocked |= g.qmask;
-                continue;
-            }
-            bool ok = diagonal(g) || ((R >> g.target) & 1);
-            if (g.kind == G_SWAP) ok = ((R >> g.target) & 1) && ((R >> g.target2) & 1);
-            if (ok) take.push_back(i);
-            else blocked |= g.qmask;
-        }
+        executable(R, &take);
         // --- stages: a stage holds dense ops on at most log_e distinct resident targets (its
         // register bits) and diagonal ops on any qubits; a quantum swap ends it
         ps.stage_begin = int(stages.size());
