@@ -368,6 +368,19 @@ def test_staged_every_variant(q, oracle_mod, dtype, m, le):
         s.close()
 
 
+@pytest.mark.parametrize("n,dtype,m,le,most", [(33, "c128", 12, 4, 14), (33, "c128", 11, 4, 19), (33, "c128", 10, 4, 24),
+                                                 (34, "c64", 12, 4, 17)])
+def test_staged_pass_count_full_size(q, n, dtype, m, le, most):
+    """The scheduler's resident-set choice on the full-size brickwork (the plan alone: no state is
+    allocated). Each pass can run a light cone of several layers over a window of neighbouring
+    qubits; the pass count bounds the HBM traffic of the plan."""
+    c = q.parse_circuit(wl.brickwork_circuit(n, 20, seed=21 if dtype == "c128" else 31))
+    p = q.Plan(c, dtype, method="staged", lds_qubits=m, lds_regs=le)
+    print(f"brickwork {n} {dtype} m={m}: {p.info['passes']} passes", flush=True)
+    assert p.info["passes"] <= most
+    p.close()
+
+
 @pytest.mark.parametrize("dtype", DTYPES)
 @pytest.mark.parametrize("seed", [1, 2])
 def test_staged_config0(q, oracle_mod, dtype, seed):
