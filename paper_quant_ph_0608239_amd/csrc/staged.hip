@@ -560,29 +560,7 @@ int staged::staged_schedule(int n, int dtype, int m, int log_e, const std::vecto
         // --- stages: a stage holds dense ops on at most log_e distinct resident targets (its
         // register bits) and diagonal ops on any qubits; a quantum swap ends it
         ps.stage_begin = int(stages.size());
-        std::vector<HOp> sops;
-        SStage cur{};
-        cur.swap_p = cur.swap_q = -1;
-        uint32_t rbset = 0;
-        int nrb = 0;
-        auto close_stage = [&]() {
-            emit_stage(cur, rbset, log_e, m, dtype, localof, ps.R, sops, stages, rounds, ops);
-            sops.clear();
-            cur = SStage{};
-            cur.swap_p = cur.swap_q = -1;
-            rbset = 0;
-            nrb = 0;
-        };
-        for (size_t i : take) {
-            const GInfo &g = gi[i];
-            if (g.kind == G_SWAP) {
-                cur.swap_p = localof[g.target];
-                cur.swap_q = localof[g.target2];
-                cur.swap_lcm = local_mask(g.controls);
-                cur.swap_gcm = g.controls & ~R;
-                close_stage();
-                continue;
-            }
+        auto make_hop = [&](const GInfo &g) {
             HOp h{};
             h.target = g.target;
             h.controls = g.controls;
@@ -608,15 +586,105 @@ int staged::staged_schedule(int n, int dtype, int m, int log_e, const std::vecto
                 h.dense = true;
                 h.lb = localof[g.target];
                 memcpy(h.m, g.m, sizeof(h.m));
-                if (!((rbset >> h.lb) & 1)) {
+            }
+            return h;
+        };
+        bool has_swap = false;
+        for (size_t i : take) has_swap = has_swap || gi[i].kind == G_SWAP;
+        if (has_swap) {
+            // circuit order: a stage closes at a fifth register bit or at a quantum swap
+            std::vector<HOp> sops;
+            SStage cur{};
+            cur.swap_p = cur.swap_q = -1;
+            uint32_t rbset = 0;
+            int nrb = 0;
+            auto close_stage = [&]() {
+                emit_stage(cur, rbset, log_e, m, dtype, localof, ps.R, sops, stages, rounds, ops);
+                sops.clear();
+                cur = SStage{};
+                cur.swap_p = cur.swap_q = -1;
+                rbset = 0;
+                nrb = 0;
+            };
+            for (size_t i : take) {
+                const GInfo &g = gi[i];
+                if (g.kind == G_SWAP) {
+                    cur.swap_p = localof[g.target];
+                    cur.swap_q = localof[g.target2];
+                    cur.swap_lcm = local_mask(g.controls);
+                    cur.swap_gcm = g.controls & ~R;
+                    close_stage();
+                    continue;
+                }
+                const HOp h = make_hop(g);
+                if (h.dense && !((rbset >> h.lb) & 1)) {
                     if (nrb == log_e) close_stage();
                     rbset |= 1u << h.lb;
                     ++nrb;
                 }
+                sops.push_back(h);
             }
-            sops.push_back(h);
+            if (!sops.empty() || int(stages.size()) == ps.stage_begin) close_stage();
+        } else {
+            // Stages in dependency order, each on the register-bit set S that runs the most dense ops:
+            // the first log_e distinct targets in circuit order, or a window of log_e consecutive
+            // local bits (on neighbour-coupled circuits a stage then runs a light cone of several
+            // layers on its qubits, and the block goes through LDS fewer times). Within the pass the
+            // same rule as for passes holds: an op runs when no earlier op left behind holds one of
+            // its qubits, and it is diagonal or its target is in S.
+            std::vector<size_t> rem(take);
+            auto stage_take = [&](uint32_t S, std::vector<size_t> *sel, std::vector<size_t> *rest) {
+                int dense = 0, all = 0;
+                uint64_t blocked = 0;
+                for (size_t i : rem) {
+                    const GInfo &g = gi[i];
+                    bool ok = !(g.qmask & blocked) && (diagonal(g) || ((S >> localof[g.target]) & 1));
+                    if (ok) {
+                        ++all;
+                        if (!diagonal(g)) ++dense;
+                        if (sel) sel->push_back(i);
+                    } else {
+                        blocked |= g.qmask;
+                        if (rest) rest->push_back(i);
+                    }
+                }
+                return std::make_pair(dense, all);
+            };
+            while (!rem.empty()) {
+                uint32_t S = 0;
+                int ns = 0;
+                for (size_t i : rem) {
+                    const GInfo &g = gi[i];
+                    if (diagonal(g) || ((S >> localof[g.target]) & 1)) continue;
+                    if (ns == log_e) break;
+                    S |= 1u << localof[g.target];
+                    ++ns;
+                }
+                std::pair<int, int> best = stage_take(S, nullptr, nullptr);
+                for (int a = 0; a + log_e <= m; ++a) {
+                    const uint32_t Sw = ((1u << log_e) - 1) << a;
+                    const std::pair<int, int> c = stage_take(Sw, nullptr, nullptr);
+                    if (c.first > best.first || (c.first == best.first && c.second > best.second)) {
+                        best = c;
+                        S = Sw;
+                    }
+                }
+                std::vector<size_t> sel, rest;
+                stage_take(S, &sel, &rest);
+                if (sel.empty()) return set_error(QSIM_EINVAL, "staged: stage scheduler made no progress");
+                std::vector<HOp> sops;
+                uint32_t rbset = 0;
+                for (size_t i : sel) {
+                    const HOp h = make_hop(gi[i]);
+                    if (h.dense) rbset |= 1u << h.lb;
+                    sops.push_back(h);
+                }
+                SStage cur{};
+                cur.swap_p = cur.swap_q = -1;
+                emit_stage(cur, rbset, log_e, m, dtype, localof, ps.R, sops, stages, rounds, ops);
+                rem.swap(rest);
+            }
         }
-        if (!sops.empty() || int(stages.size()) == ps.stage_begin) close_stage();
         ps.stage_end = int(stages.size());
         // direct memory access for the first / last stage when its register bits avoid the low run
         auto low_free = [&](const SStage &st) {
