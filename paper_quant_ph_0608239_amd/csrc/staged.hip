@@ -46,6 +46,20 @@ __global__ __launch_bounds__(1 << LOG_T, MINW) void k_staged(T *__restrict__ a, 
     run_block<T, LOG_E, LOG_T>(a, pass, blockIdx.x, as_const(stages), as_const(rounds), as_const(ops), lds, false);
 }
 
+// The same pass with a buffer of half the block (every LDS round trip in two halves): twice the
+// workgroups per CU where LDS, not registers, bounds the occupancy.
+template <typename T, int LOG_E, int LOG_T, int MINW>
+__global__ __launch_bounds__(1 << LOG_T, MINW) void k_staged_half(T *__restrict__ a, const SPass *__restrict__ passp,
+                                                                  const SStage *__restrict__ stages,
+                                                                  const SRound *__restrict__ rounds,
+                                                                  const SOp *__restrict__ ops)
+{
+    using C = typename Vec<T>::C;
+    __shared__ C lds[lds_slots<T>(LOG_E + LOG_T - 1)];
+    const SPass pass = ldc<SPass>(as_const(passp));
+    run_block_half<T, LOG_E, LOG_T>(a, pass, blockIdx.x, as_const(stages), as_const(rounds), as_const(ops), lds);
+}
+
 }  // namespace
 
 namespace staged {
@@ -235,6 +249,13 @@ void carry_row_phases(int n, std::vector<GInfo> &g)
 }  // namespace
 
 // kernel variants: (amplitudes per thread, threads) per dtype; see launch_pass
+// block shapes that have a half-buffer kernel
+static bool half_variant(int dtype, int log_e, int log_t)
+{
+    if (dtype == QSIM_C128) return log_e == 4 && log_t >= 6 && log_t <= 8;
+    return log_e == 5 && log_t >= 6 && log_t <= 8;
+}
+
 bool staged::staged_variant_ok(int dtype, int log_e, int log_t)
 {
     if (log_t < 6 || log_t > 10) return false;
@@ -269,6 +290,47 @@ bool commute(const HOp &a, const HOp &b)
 
 }  // namespace
 
+// Thread bits of a stage, lowest lane first. LDS slot s(e) = e + (e >> P) (one pad slot per 2^P)
+// puts a lane bit at local position b < 2P on the bank group of b mod P (and higher positions on
+// none), so the first P lanes take one position from each residue class where the register bits
+// leave one: then the 2^P lanes of a wide LDS access hit distinct bank groups. The low run keeps its
+// order (0, 1, ... are their own classes), so stages that read memory directly stay coalesced.
+// nfix local bits fb[i] are pinned at thread positions fj[i] (the split bits of the half-buffer
+// exchanges: either at a position >= P, or a low-run bit at its own position); the bank-class picks
+// and then the remaining bits in ascending order take the free positions.
+static void order_threads(SStage &cur, uint32_t rbset, int m, int log_e, int dtype, const uint8_t *R, int nfix,
+                          const int *fj, const int *fb)
+{
+    const int P = dtype == QSIM_C128 ? 4 : 5;
+    const int lt = m - log_e;
+    uint32_t left = ((1u << m) - 1) & ~rbset;
+    uint32_t taken_pos = 0, done_class = 0;
+    for (int i = 0; i < nfix; ++i) {
+        cur.tbits[fj[i]] = uint8_t(fb[i]);
+        left &= ~(1u << fb[i]);
+        taken_pos |= 1u << fj[i];
+        if (fb[i] < 2 * P) done_class |= 1u << (fb[i] % P);
+    }
+    int jt = 0;
+    for (int c = 0; c < P; ++c) {
+        if ((done_class >> c) & 1) continue;
+        for (int b = c; b < 2 * P && b < m; b += P)
+            if ((left >> b) & 1) {
+                while ((taken_pos >> jt) & 1) ++jt;
+                if (jt >= lt) break;
+                cur.tbits[jt++] = uint8_t(b);
+                left &= ~(1u << b);
+                break;
+            }
+    }
+    for (int b = 0; b < m; ++b)
+        if ((left >> b) & 1) {
+            while ((taken_pos >> jt) & 1) ++jt;
+            cur.tbits[jt++] = uint8_t(b);
+        }
+    for (int j = 0; j < lt; ++j) cur.ptb[j] = R[cur.tbits[j]];
+}
+
 // Close a stage: fix its register bits, turn every op's condition into its register part (pair or
 // element masks) and its thread part, and order the ops into rounds. An op goes to the earliest
 // round in which it runs after every earlier op of the stage it does not commute with (within a
@@ -287,27 +349,8 @@ static void emit_stage(SStage cur, uint32_t rbset, int log_e, int m, int dtype, 
         }
     for (int s = 0, j = 0; s < m; ++s)
         if ((rbset >> s) & 1) cur.rb[j++] = uint8_t(s);
-    // Thread bits, lowest lane first. LDS slot s(e) = e + (e >> P) (one pad slot per 2^P) puts a
-    // lane bit at local position b < 2P on the bank group of b mod P (and higher positions on none),
-    // so the first P lanes take one position from each residue class where the register bits leave
-    // one: then the 2^P lanes of a wide LDS access hit distinct bank groups. The low run keeps its
-    // order (0, 1, ... are their own classes), so stages that read memory directly stay coalesced.
-    {
-        const int P = dtype == QSIM_C128 ? 4 : 5;
-        uint32_t left = ((1u << m) - 1) & ~rbset;
-        int jt = 0;
-        for (int c = 0; c < P && jt < m - log_e; ++c)
-            for (int b = c; b < 2 * P && b < m; b += P)
-                if ((left >> b) & 1) {
-                    cur.tbits[jt++] = uint8_t(b);
-                    left &= ~(1u << b);
-                    break;
-                }
-        for (int b = 0; b < m; ++b)
-            if ((left >> b) & 1) cur.tbits[jt++] = uint8_t(b);
-    }
+    order_threads(cur, rbset, m, log_e, dtype, R, 0, nullptr, nullptr);
     for (int j = 0; j < log_e; ++j) cur.prb[j] = R[cur.rb[j]];
-    for (int j = 0; j < m - log_e; ++j) cur.ptb[j] = R[cur.tbits[j]];
     auto rank_of = [&](int lb) { return __builtin_popcount(rbset & ((1u << lb) - 1)); };
     const size_t N = sops.size();
     std::vector<SOp> rec(N);
@@ -461,6 +504,81 @@ static void emit_stage(SStage cur, uint32_t rbset, int log_e, int m, int dtype, 
 
 // Schedule `gates` for an n-qubit state into passes of m resident qubits with 2^log_e amplitudes per
 // thread; passes, stages, rounds and ops are appended to the given tables (indices are absolute).
+// Half-buffer form of a pass: for every LDS round trip (load layout -> first stage, stage -> next
+// stage, last stage -> store layout) pick a split bit that sits at the same thread position in both
+// layouts (in the load/store layout, local bit j is at thread position j), then pin those positions in
+// each stage's thread order. A split position >= 6 (a wave bit) gives each half whole wavefronts, and
+// a split bit >= 2P leaves the bank groups of the other bits unchanged, so those are preferred. Returns false (the pass keeps the full buffer) if a round trip has no such bit or the
+// pass ends a stage with a quantum swap.
+static bool assign_half(SPass &ps, std::vector<SStage> &stages, int m, int log_e, int dtype)
+{
+    const int lt = m - log_e, P = dtype == QSIM_C128 ? 4 : 5;
+    if (lt <= P) return false;
+    const int s0 = ps.stage_begin, ns = ps.stage_end - ps.stage_begin;
+    std::vector<uint32_t> T(static_cast<size_t>(ns)), rbs(static_cast<size_t>(ns));
+    for (int s = 0; s < ns; ++s) {
+        const SStage &st = stages[size_t(s0 + s)];
+        if (st.swap_p >= 0) return false;
+        uint32_t rb = 0;
+        for (int j = 0; j < log_e; ++j) rb |= 1u << st.rb[j];
+        rbs[size_t(s)] = rb;
+        T[size_t(s)] = ((1u << m) - 1) & ~rb;
+    }
+    std::vector<int> bi(size_t(ns), -1), ji(size_t(ns), -1), bo(size_t(ns), -1), jo(size_t(ns), -1);
+    // best (b, j) with b in the candidate set `cand` (load/store: b == j), consistent with stage s's
+    // incoming split (one bit per position)
+    // (b, j) for the round trip out of stage s (s < 0: into stage 0 from the load layout), b in
+    // `cand`; in the load/store layout b == j. A position below P holds a low-run bit at its own
+    // position only (a stage that reads or writes memory directly keeps the low run on its first
+    // lanes in order); one bit per position within each stage.
+    auto pick = [&](int s, uint32_t cand, bool fixed_layout, int &b_out, int &j_out) {
+        int best = -1;
+        for (int j = 0; j < lt; ++j)
+            for (int b = 0; b < m; ++b) {
+                if (!((cand >> b) & 1) || (fixed_layout && b != j)) continue;
+                if ((j < P || b < P) && b != j) {
+                    // a low-run bit away from its own lane: only between stages that do not touch memory
+                    if (j < P) continue;
+                    if (s < 0 || (s == 0 && (ps.direct & 1)) || (s + 1 == ns - 1 && (ps.direct & 2)) || s == ns - 1) continue;
+                }
+                if (s >= 0 && ji[size_t(s)] >= 0 && ((j == ji[size_t(s)]) != (b == bi[size_t(s)]))) continue;
+                const int sc = (j >= 6 ? 10000 : 0) + (b >= 2 * P ? 1000 : 0) + (b >= P ? 500 : 0) + 32 * j + b;
+                if (sc > best) {
+                    best = sc;
+                    b_out = b;
+                    j_out = j;
+                }
+            }
+        return best >= 0;
+    };
+    if (!(ps.direct & 1) && !pick(-1, T[0], true, bi[0], ji[0])) return false;
+    for (int s = 0; s + 1 < ns; ++s) {
+        if (!pick(s, T[size_t(s)] & T[size_t(s + 1)], false, bo[size_t(s)], jo[size_t(s)])) return false;
+        bi[size_t(s + 1)] = bo[size_t(s)];
+        ji[size_t(s + 1)] = jo[size_t(s)];
+    }
+    if (!(ps.direct & 2) && !pick(ns - 1, T[size_t(ns - 1)], true, bo[size_t(ns - 1)], jo[size_t(ns - 1)])) return false;
+    for (int s = 0; s < ns; ++s) {
+        SStage &st = stages[size_t(s0 + s)];
+        int fj[2], fb[2], nf = 0;
+        if (ji[size_t(s)] >= 0) {
+            fj[nf] = ji[size_t(s)];
+            fb[nf++] = bi[size_t(s)];
+        }
+        if (jo[size_t(s)] >= 0 && jo[size_t(s)] != ji[size_t(s)]) {
+            fj[nf] = jo[size_t(s)];
+            fb[nf++] = bo[size_t(s)];
+        }
+        order_threads(st, rbs[size_t(s)], m, log_e, dtype, ps.R, nf, fj, fb);
+        st.hb_in = uint8_t(std::max(bi[size_t(s)], 0));
+        st.hj_in = uint8_t(std::max(ji[size_t(s)], 0));
+        st.hb_out = uint8_t(std::max(bo[size_t(s)], 0));
+        st.hj_out = uint8_t(std::max(jo[size_t(s)], 0));
+    }
+    ps.direct |= 4;
+    return true;
+}
+
 int staged::staged_schedule(int n, int dtype, int m, int log_e, const std::vector<qsim_gate> &gates,
                             std::vector<SPass> &passes, std::vector<SStage> &stages, std::vector<SRound> &rounds,
                             std::vector<SOp> &ops)
@@ -695,6 +813,7 @@ int staged::staged_schedule(int n, int dtype, int m, int log_e, const std::vecto
         ps.direct = 0;
         if (low_free(stages[size_t(ps.stage_begin)])) ps.direct |= 1;
         if (low_free(stages[size_t(ps.stage_end - 1)]) && stages[size_t(ps.stage_end - 1)].swap_p < 0) ps.direct |= 2;
+        if (half_variant(dtype, log_e, m - log_e)) assign_half(ps, stages, m, log_e, dtype);
         passes.push_back(ps);
         for (size_t i : take) done[i] = 1;
         ndone += take.size();
@@ -766,9 +885,29 @@ static void launch_variant(StagedPlan *p, qsim_state *s, size_t i)
                        static_cast<T *>(s->data), p->d_passes + i, p->d_stages, p->d_rounds, p->d_ops);
 }
 
+template <typename T, int LE, int LT, int MW>
+static void launch_half(StagedPlan *p, qsim_state *s, size_t i)
+{
+    hipLaunchKernelGGL((k_staged_half<T, LE, LT, MW>), dim3(unsigned(dim(p->n - p->m))), dim3(1 << LT), 0, s->stream,
+                       static_cast<T *>(s->data), p->d_passes + i, p->d_stages, p->d_rounds, p->d_ops);
+}
+
 static int launch_pass(StagedPlan *p, qsim_state *s, size_t i)
 {
     const int v = p->log_e * 16 + p->log_t;
+    if (p->passes[i].direct & 4) {
+        switch ((p->dtype == QSIM_C128 ? 256 : 0) + v) {
+        case 256 + 4 * 16 + 6: launch_half<double, 4, 6, 3>(p, s, i); break;
+        case 256 + 4 * 16 + 7: launch_half<double, 4, 7, 3>(p, s, i); break;
+        case 256 + 4 * 16 + 8: launch_half<double, 4, 8, 3>(p, s, i); break;
+        case 5 * 16 + 6: launch_half<float, 5, 6, 3>(p, s, i); break;
+        case 5 * 16 + 7: launch_half<float, 5, 7, 3>(p, s, i); break;
+        case 5 * 16 + 8: launch_half<float, 5, 8, 3>(p, s, i); break;
+        default: return set_error(QSIM_EINVAL, "staged: no half-buffer kernel for this block shape");
+        }
+        QSIM_HIP(hipGetLastError());
+        return QSIM_OK;
+    }
     if (p->dtype == QSIM_C128) {
         switch (v) {
         case 3 * 16 + 7: launch_variant<double, 3, 7, 4>(p, s, i); break;

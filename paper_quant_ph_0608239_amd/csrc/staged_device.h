@@ -55,7 +55,10 @@ struct SStage {
     int32_t swap_p;               // stage-end local swap (quantum swap of two resident qubits), -1 if none
     int32_t swap_q;
     uint32_t swap_lcm;            // its local condition
-    uint32_t pad;
+    // half-buffer passes: the LDS round trip into this stage (from the previous stage, or from the
+    // load layout) and the one out of it (to the next stage, or to the store layout) each run in two
+    // halves split by local bit hb_* at thread position hj_* of both layouts
+    uint8_t hb_in, hj_in, hb_out, hj_out;
     uint64_t swap_gcm;            // its condition on non-resident bits
     uint8_t prb[8];               // index bit (physical qubit) of each register bit
     uint8_t ptb[kMaxLogT + 6];    // index bit of each thread bit, lowest lane first
@@ -68,7 +71,8 @@ struct SPass {
     int32_t direct;     // bit 0: the first stage loads its registers straight from memory; bit 1: the
                         // last stage stores them straight to memory (no LDS round trip). Set when the
                         // stage's register bits avoid the low run, so that its thread bits keep
-                        // consecutive lanes on consecutive amplitudes
+                        // consecutive lanes on consecutive amplitudes. Bit 2: every LDS round trip of
+                        // the pass has a split bit, and it runs with a half-size LDS buffer
     uint8_t R[16];      // physical bit of local bit s, ascending
 };
 
@@ -367,6 +371,32 @@ __device__ __forceinline__ void round_bit(typename Vec<T>::C *x, const SRound &r
     }
 }
 
+// all rounds of a stage on the registers x (in the stage's layout; et: the thread's local index part)
+template <typename T, int LOG_E>
+__device__ __forceinline__ void run_rounds(typename Vec<T>::C *x, const SStage &st, cptr<SRound> rounds, cptr<SOp> ops,
+                                           uint32_t et, uint64_t base)
+{
+    constexpr int E = 1 << LOG_E;
+    for (int ri = st.round_begin; ri < st.round_end; ++ri) {
+        const SRound rd = ldc<SRound>(rounds + ri);
+        round_bit<T, E, 0>(x, rd, ops, et, base);
+        round_bit<T, E, 1>(x, rd, ops, et, base);
+        round_bit<T, E, 2>(x, rd, ops, et, base);
+        if constexpr (LOG_E > 3) round_bit<T, E, (LOG_E > 3 ? 3 : 0)>(x, rd, ops, et, base);
+        if constexpr (LOG_E > 4) round_bit<T, E, (LOG_E > 4 ? 4 : 0)>(x, rd, ops, et, base);
+        for (int oi = rd.seg[kLists * LOG_E]; oi < rd.seg[kLists * LOG_E + 1]; ++oi) {
+            const SOp op = ldc<SOp>(ops + oi);
+            if ((base & op.gcm) != op.gcm) continue;
+            op_flip<T, E>(x, op, et);
+        }
+        for (int oi = rd.seg[kLists * LOG_E + 1]; oi < rd.seg[kLists * LOG_E + 2]; ++oi) {
+            const SOp op = ldc<SOp>(ops + oi);
+            if ((base & op.gcm) != op.gcm) continue;
+            op_diag<T, E>(x, op, et, base);
+        }
+    }
+}
+
 // Addressing of a block: block `blk` of a pass holds the 2^M amplitudes whose index bits outside the
 // resident set R equal the bits of blk. In the load/store layout, thread t and element k hold local
 // index k * NT + t, so consecutive threads take consecutive local indices (contiguous runs).
@@ -492,24 +522,7 @@ __device__ __forceinline__ void run_stages(T *__restrict__ a, const SPass &pass,
 #pragma unroll
             for (int r = 0; r < E; ++r) x[r] = lds[ls + slot<T>(er[r])];
         }
-        for (int ri = st.round_begin; ri < st.round_end; ++ri) {
-            const SRound rd = ldc<SRound>(rounds + ri);
-            round_bit<T, E, 0>(x, rd, ops, et, base);
-            round_bit<T, E, 1>(x, rd, ops, et, base);
-            round_bit<T, E, 2>(x, rd, ops, et, base);
-            if constexpr (LOG_E > 3) round_bit<T, E, (LOG_E > 3 ? 3 : 0)>(x, rd, ops, et, base);
-            if constexpr (LOG_E > 4) round_bit<T, E, (LOG_E > 4 ? 4 : 0)>(x, rd, ops, et, base);
-            for (int oi = rd.seg[kLists * LOG_E]; oi < rd.seg[kLists * LOG_E + 1]; ++oi) {
-                const SOp op = ldc<SOp>(ops + oi);
-                if ((base & op.gcm) != op.gcm) continue;
-                op_flip<T, E>(x, op, et);
-            }
-            for (int oi = rd.seg[kLists * LOG_E + 1]; oi < rd.seg[kLists * LOG_E + 2]; ++oi) {
-                const SOp op = ldc<SOp>(ops + oi);
-                if ((base & op.gcm) != op.gcm) continue;
-                op_diag<T, E>(x, op, et, base);
-            }
-        }
+        run_rounds<T, LOG_E>(x, st, rounds, ops, et, base);
         if (out_mem) break;  // stored below, after the loop
         __syncthreads();  // every thread has read this stage's inputs before anyone overwrites LDS
         if (st.swap_p >= 0 && (base & st.swap_gcm) == st.swap_gcm) {
@@ -584,6 +597,131 @@ __device__ __forceinline__ void run_block(T *__restrict__ a, const SPass &pass, 
     __syncthreads();
 }
 
+
+// ---- half-buffer passes ----------------------------------------------------------------------------
+// Local index v with bit b removed (the bits above b move down one place): the slot of an element in
+// a buffer that holds one half of the block, the half with a fixed value of bit b.
+__device__ __forceinline__ uint32_t squeeze(uint32_t v, uint32_t b)
+{
+    const uint32_t low = (1u << b) - 1;
+    return (v & low) | ((v >> 1) & ~low);
+}
+
+// Local index parts of a stage's layout: thread t holds et | er[r] in register r.
+template <int LOG_E, int LOG_T>
+__device__ __forceinline__ void stage_layout(const SStage &st, uint32_t &et, uint32_t *er)
+{
+    const int t = threadIdx.x;
+    et = 0;
+#pragma unroll
+    for (int j = 0; j < LOG_T; ++j) et |= uint32_t((t >> j) & 1) << st.tbits[j];
+#pragma unroll
+    for (int r = 0; r < (1 << LOG_E); ++r) {
+        uint32_t v = 0;
+#pragma unroll
+        for (int j = 0; j < LOG_E; ++j)
+            if ((r >> j) & 1) v |= 1u << st.rb[j];
+        er[r] = v;
+    }
+}
+
+// One LDS round trip of a half-buffer pass: registers x move from layout A (thread part at, register
+// parts ar[r]) to layout B (bt, br[r]) through a buffer of half the block. Local bit b sits at thread
+// position j in both layouts, so all elements of a thread lie in the half of its own bit j: the
+// threads with bit j = 0 exchange first, then the others. pre: start with a barrier (the buffer may
+// still be being read).
+template <typename T, int E>
+__device__ __forceinline__ void exchange_half(typename Vec<T>::C *x, typename Vec<T>::C *lds, uint32_t at,
+                                              const uint32_t *ar, uint32_t bt, const uint32_t *br, uint32_t b,
+                                              uint32_t j, bool pre)
+{
+    const uint32_t mine = (uint32_t(threadIdx.x) >> j) & 1;
+    const int wls = slot<T>(int(squeeze(at, b))), rls = slot<T>(int(squeeze(bt, b)));
+#pragma unroll
+    for (uint32_t p = 0; p < 2; ++p) {
+        if (pre || p) __syncthreads();
+        if (mine == p) {
+#pragma unroll
+            for (int r = 0; r < E; ++r) lds[wls + slot<T>(int(squeeze(ar[r], b)))] = x[r];
+        }
+        __syncthreads();
+        if (mine == p) {
+#pragma unroll
+            for (int r = 0; r < E; ++r) x[r] = lds[rls + slot<T>(int(squeeze(br[r], b)))];
+        }
+    }
+}
+
+// Process block `blk` of a half-buffer pass (SPass::direct bit 2): as run_block, with every LDS round
+// trip split in two by the stages' split bits. `lds` holds lds_slots<T>(LOG_E + LOG_T - 1) amplitudes.
+template <typename T, int LOG_E, int LOG_T>
+__device__ __forceinline__ void run_block_half(T *__restrict__ a, const SPass &pass, uint64_t blk, cptr<SStage> stages,
+                                               cptr<SRound> rounds, cptr<SOp> ops, typename Vec<T>::C *lds)
+{
+    using C = typename Vec<T>::C;
+    constexpr int E = 1 << LOG_E;
+    const int t = threadIdx.x;
+    const uint64_t base = block_base<LOG_E + LOG_T>(pass, blk);
+    uint32_t lr[E];  // register parts of the load/store layout (thread part: t)
+#pragma unroll
+    for (int k = 0; k < E; ++k) lr[k] = uint32_t(k) << LOG_T;
+    C x[E];
+    SStage st = ldc<SStage>(stages + pass.stage_begin);
+    uint32_t et, er[E];
+    stage_layout<LOG_E, LOG_T>(st, et, er);
+    if (pass.direct & 1) {
+        uint64_t gt = base;
+#pragma unroll
+        for (int j = 0; j < LOG_T; ++j)
+            if ((t >> j) & 1) gt |= uint64_t(1) << st.ptb[j];
+        const C *ag = reinterpret_cast<const C *>(a) + gt;
+#pragma unroll
+        for (int r = 0; r < E; ++r) {
+            uint64_t v = 0;
+#pragma unroll
+            for (int j = 0; j < LOG_E; ++j)
+                if ((r >> j) & 1) v |= uint64_t(1) << st.prb[j];
+            x[r] = ld_nt(ag + v);
+        }
+    } else {
+        const C *ag = reinterpret_cast<const C *>(a) + (base | lane_part<LOG_T>(pass, t));
+#pragma unroll
+        for (int k = 0; k < E; ++k) x[k] = ld_nt(ag + elem_part<LOG_E, LOG_T>(pass, k));
+        exchange_half<T, E>(x, lds, uint32_t(t), lr, et, er, st.hb_in, st.hj_in, false);
+    }
+    for (int si = pass.stage_begin;;) {
+        run_rounds<T, LOG_E>(x, st, rounds, ops, et, base);
+        if (++si == pass.stage_end) break;
+        const SStage nx = ldc<SStage>(stages + si);
+        uint32_t nt, nr[E];
+        stage_layout<LOG_E, LOG_T>(nx, nt, nr);
+        exchange_half<T, E>(x, lds, et, er, nt, nr, st.hb_out, st.hj_out, true);
+        st = nx;
+        et = nt;
+#pragma unroll
+        for (int r = 0; r < E; ++r) er[r] = nr[r];
+    }
+    if (pass.direct & 2) {
+        uint64_t gt = base;
+#pragma unroll
+        for (int j = 0; j < LOG_T; ++j)
+            if ((t >> j) & 1) gt |= uint64_t(1) << st.ptb[j];
+        C *agw = reinterpret_cast<C *>(a) + gt;
+#pragma unroll
+        for (int r = 0; r < E; ++r) {
+            uint64_t v = 0;
+#pragma unroll
+            for (int j = 0; j < LOG_E; ++j)
+                if ((r >> j) & 1) v |= uint64_t(1) << st.prb[j];
+            st_nt(agw + v, x[r]);
+        }
+    } else {
+        exchange_half<T, E>(x, lds, et, er, uint32_t(t), lr, st.hb_out, st.hj_out, true);
+        C *agw = reinterpret_cast<C *>(a) + (base | lane_part<LOG_T>(pass, t));
+#pragma unroll
+        for (int k = 0; k < E; ++k) st_nt(agw + elem_part<LOG_E, LOG_T>(pass, k), x[k]);
+    }
+}
 
 // host: append the schedule of one circuit (see staged.hip)
 int staged_schedule(int n, int dtype, int m, int log_e, const std::vector<qsim_gate> &gates, std::vector<SPass> &passes,
