@@ -253,7 +253,7 @@ void carry_row_phases(int n, std::vector<GInfo> &g)
 static bool half_variant(int dtype, int log_e, int log_t)
 {
     if (dtype == QSIM_C128) return log_e == 4 && log_t >= 6 && log_t <= 8;
-    return log_e == 5 && log_t >= 6 && log_t <= 8;
+    return log_e == 5 && log_t >= 6 && log_t <= 8;  // with 16 amplitudes per thread the full buffer measured faster
 }
 
 bool staged::staged_variant_ok(int dtype, int log_e, int log_t)

@@ -226,36 +226,46 @@ __device__ __forceinline__ void xor_sign(double &v, uint32_t t)
 __device__ __forceinline__ void xor_sign(float &v, uint32_t t) { v = __builtin_bit_cast(float, __builtin_bit_cast(uint32_t, v) ^ t); }
 
 // A dense op with a fused flip chosen per pair (register bits) or per block: in the pairs that take
-// it, the second amplitude changes sign before the 2x2 (column flip) or after it (row flip). The
-// per-pair sign words are wave-uniform.
+// it, the second amplitude changes sign before the 2x2 (column flip) or after it (row flip). Those
+// pairs use the 2x2 with column 1 or row 1 negated instead; the choice between the two coefficient
+// sets is wave-uniform (scalar selects), so the pair costs the same FMAs as an unconditional one.
+// Negating coefficients gives the same bits as negating the data (rounding is sign-symmetric).
 template <typename T, int E, int RB>
 __device__ __forceinline__ void op_dense_alt_uniform(typename Vec<T>::C *x, const SOp &op, uint64_t base)
 {
     const T *c = coef<T>(op);
-    U2<T> u;
+    U2<T> u, v;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         u.r[k] = c[2 * k];
         u.i[k] = c[2 * k + 1];
     }
+    const bool col = op.alt_col != 0;
+    v = u;
+    v.r[1] = col ? -u.r[1] : u.r[1];
+    v.i[1] = col ? -u.i[1] : u.i[1];
+    v.r[2] = col ? u.r[2] : -u.r[2];
+    v.r[3] = -u.r[3];
+    v.i[3] = -u.i[3];
     const uint32_t am = (base & op.galt) == op.galt ? op.amask : 0u;
-    const uint32_t col = op.alt_col ? 0x80000000u : 0u, row = op.alt_col ? 0u : 0x80000000u;
 #pragma unroll
     for (int r = 0; r < E; ++r) {
         if ((r >> RB) & 1) continue;
         const int p = (r & ((1 << RB) - 1)) | ((r >> (RB + 1)) << RB);
         const bool neg = (am >> p) & 1;
-        const uint32_t tc = neg ? col : 0u, tr = neg ? row : 0u;
-        xor_sign(x[r | (1 << RB)].x, tc);
-        xor_sign(x[r | (1 << RB)].y, tc);
-        pair2x2_rc<T, true>(x[r], x[r | (1 << RB)], u);
-        xor_sign(x[r | (1 << RB)].x, tr);
-        xor_sign(x[r | (1 << RB)].y, tr);
+        U2<T> w;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            w.r[k] = neg ? v.r[k] : u.r[k];
+            w.i[k] = neg ? v.i[k] : u.i[k];
+        }
+        pair2x2_rc<T, true>(x[r], x[r | (1 << RB)], w);
     }
 }
 
 // A dense op with a fused flip chosen per lane (a thread bit): every pair of the lanes that take it
-// uses the 2x2 with row 1 (or column 1) negated.
+// uses the 2x2 with row 1 (or column 1) negated. (A sign xor of the data instead needs the flip on
+// one side of the 2x2 or the other; a branch on that side made the compiler copy the amplitudes.)
 template <typename T, int E, int RB>
 __device__ __forceinline__ void op_dense_alt_lane(typename Vec<T>::C *x, const SOp &op, uint32_t et, uint64_t base)
 {
