@@ -492,19 +492,19 @@ __device__ __forceinline__ void run_stages(T *__restrict__ a, const SPass &pass,
         uint32_t et = 0;
 #pragma unroll
         for (int j = 0; j < LOG_T; ++j) et |= uint32_t((t >> j) & 1) << st.tbits[j];
-        uint32_t er[E];
+        int so[E];  // LDS slot offsets of the register elements (slots are additive over disjoint bits)
+        {
+            int sj[LOG_E];
 #pragma unroll
-        for (int r = 0; r < E; ++r) {
-            uint32_t v = 0;
+            for (int j = 0; j < LOG_E; ++j) sj[j] = slot<T>(int(1u << st.rb[j]));
+            so[0] = 0;
 #pragma unroll
-            for (int j = 0; j < LOG_E; ++j)
-                if ((r >> j) & 1) v |= 1u << st.rb[j];
-            er[r] = v;
+            for (int r = 1; r < E; ++r) so[r] = so[r & (r - 1)] + sj[__builtin_ctz(r)];
         }
         const int ls = slot<T>(et);
         const bool first = si == pass.stage_begin, last = si == pass.stage_end - 1;
         const bool in_mem = first && (pass.direct & 1), out_mem = last && (pass.direct & 2);
-        // memory address of element (t, r) in this stage's layout: base | dep(et) | dep(er[r])
+        // memory address of element (t, r) in this stage's layout: base | index bits of et | index bits of r's register bits
         uint64_t gt = 0;
         if (in_mem) {
 #pragma unroll
@@ -530,7 +530,7 @@ __device__ __forceinline__ void run_stages(T *__restrict__ a, const SPass &pass,
             }
         } else {
 #pragma unroll
-            for (int r = 0; r < E; ++r) x[r] = lds[ls + slot<T>(er[r])];
+            for (int r = 0; r < E; ++r) x[r] = lds[ls + so[r]];
         }
         run_rounds<T, LOG_E>(x, st, rounds, ops, et, base);
         if (out_mem) break;  // stored below, after the loop
@@ -539,7 +539,10 @@ __device__ __forceinline__ void run_stages(T *__restrict__ a, const SPass &pass,
             // stage-end quantum swap of two resident qubits: a permutation of the LDS slots
 #pragma unroll
             for (int r = 0; r < E; ++r) {
-                uint32_t d = et | er[r];
+                uint32_t d = et;
+#pragma unroll
+                for (int j = 0; j < LOG_E; ++j)
+                    if ((r >> j) & 1) d |= 1u << st.rb[j];
                 if ((d & st.swap_lcm) == st.swap_lcm) {
                     const uint32_t bp = (d >> st.swap_p) & 1, bq = (d >> st.swap_q) & 1;
                     if (bp != bq) d ^= (1u << st.swap_p) | (1u << st.swap_q);
@@ -548,7 +551,7 @@ __device__ __forceinline__ void run_stages(T *__restrict__ a, const SPass &pass,
             }
         } else {
 #pragma unroll
-            for (int r = 0; r < E; ++r) lds[ls + slot<T>(er[r])] = x[r];
+            for (int r = 0; r < E; ++r) lds[ls + so[r]] = x[r];
         }
         __syncthreads();
     }
@@ -617,47 +620,44 @@ __device__ __forceinline__ uint32_t squeeze(uint32_t v, uint32_t b)
     return (v & low) | ((v >> 1) & ~low);
 }
 
-// Local index parts of a stage's layout: thread t holds et | er[r] in register r.
-template <int LOG_E, int LOG_T>
-__device__ __forceinline__ void stage_layout(const SStage &st, uint32_t &et, uint32_t *er)
+// Slot offsets of a stage's register elements in the half buffer split by local bit b (a thread bit,
+// so never one of the register bits rb[]): slots are additive over disjoint bits, so so[r] is the sum
+// of the offsets of r's bits, one addition per element.
+template <typename T, int LOG_E>
+__device__ __forceinline__ void half_slots(const uint8_t *rb, uint32_t b, int *so)
 {
-    const int t = threadIdx.x;
-    et = 0;
+    int sj[LOG_E];
 #pragma unroll
-    for (int j = 0; j < LOG_T; ++j) et |= uint32_t((t >> j) & 1) << st.tbits[j];
-#pragma unroll
-    for (int r = 0; r < (1 << LOG_E); ++r) {
-        uint32_t v = 0;
-#pragma unroll
-        for (int j = 0; j < LOG_E; ++j)
-            if ((r >> j) & 1) v |= 1u << st.rb[j];
-        er[r] = v;
+    for (int j = 0; j < LOG_E; ++j) {
+        const uint32_t p = rb[j];
+        sj[j] = slot<T>(int(1u << (p - (p > b ? 1u : 0u))));
     }
+    so[0] = 0;
+#pragma unroll
+    for (int r = 1; r < (1 << LOG_E); ++r) so[r] = so[r & (r - 1)] + sj[__builtin_ctz(r)];
 }
 
-// One LDS round trip of a half-buffer pass: registers x move from layout A (thread part at, register
-// parts ar[r]) to layout B (bt, br[r]) through a buffer of half the block. Local bit b sits at thread
-// position j in both layouts, so all elements of a thread lie in the half of its own bit j: the
-// threads with bit j = 0 exchange first, then the others. pre: start with a barrier (the buffer may
-// still be being read).
+// One LDS round trip of a half-buffer pass: registers x move from layout A (thread slot wls, register
+// slots wso[r]) to layout B (rls, rso[r]) through a buffer of half the block, split by a local bit that
+// sits at thread position j in both layouts: all elements of a thread lie in the half of its own bit j.
+// The threads with bit j = 0 exchange first, then the others. pre: start with a barrier (the buffer
+// may still be being read).
 template <typename T, int E>
-__device__ __forceinline__ void exchange_half(typename Vec<T>::C *x, typename Vec<T>::C *lds, uint32_t at,
-                                              const uint32_t *ar, uint32_t bt, const uint32_t *br, uint32_t b,
-                                              uint32_t j, bool pre)
+__device__ __forceinline__ void exchange_half(typename Vec<T>::C *x, typename Vec<T>::C *lds, int wls, const int *wso,
+                                              int rls, const int *rso, uint32_t j, bool pre)
 {
     const uint32_t mine = (uint32_t(threadIdx.x) >> j) & 1;
-    const int wls = slot<T>(int(squeeze(at, b))), rls = slot<T>(int(squeeze(bt, b)));
 #pragma unroll
     for (uint32_t p = 0; p < 2; ++p) {
         if (pre || p) __syncthreads();
         if (mine == p) {
 #pragma unroll
-            for (int r = 0; r < E; ++r) lds[wls + slot<T>(int(squeeze(ar[r], b)))] = x[r];
+            for (int r = 0; r < E; ++r) lds[wls + wso[r]] = x[r];
         }
         __syncthreads();
         if (mine == p) {
 #pragma unroll
-            for (int r = 0; r < E; ++r) x[r] = lds[rls + slot<T>(int(squeeze(br[r], b)))];
+            for (int r = 0; r < E; ++r) x[r] = lds[rls + rso[r]];
         }
     }
 }
@@ -672,13 +672,16 @@ __device__ __forceinline__ void run_block_half(T *__restrict__ a, const SPass &p
     constexpr int E = 1 << LOG_E;
     const int t = threadIdx.x;
     const uint64_t base = block_base<LOG_E + LOG_T>(pass, blk);
-    uint32_t lr[E];  // register parts of the load/store layout (thread part: t)
+    // load/store layout: thread t, element k at local index k * 2^LOG_T + t; its split bit is a thread
+    // bit, so the element parts move down one place in the half buffer
+    int lso[E];
 #pragma unroll
-    for (int k = 0; k < E; ++k) lr[k] = uint32_t(k) << LOG_T;
+    for (int k = 0; k < E; ++k) lso[k] = slot<T>(k << (LOG_T - 1));
     C x[E];
     SStage st = ldc<SStage>(stages + pass.stage_begin);
-    uint32_t et, er[E];
-    stage_layout<LOG_E, LOG_T>(st, et, er);
+    uint32_t et = 0;
+#pragma unroll
+    for (int j = 0; j < LOG_T; ++j) et |= uint32_t((t >> j) & 1) << st.tbits[j];
     if (pass.direct & 1) {
         uint64_t gt = base;
 #pragma unroll
@@ -697,19 +700,25 @@ __device__ __forceinline__ void run_block_half(T *__restrict__ a, const SPass &p
         const C *ag = reinterpret_cast<const C *>(a) + (base | lane_part<LOG_T>(pass, t));
 #pragma unroll
         for (int k = 0; k < E; ++k) x[k] = ld_nt(ag + elem_part<LOG_E, LOG_T>(pass, k));
-        exchange_half<T, E>(x, lds, uint32_t(t), lr, et, er, st.hb_in, st.hj_in, false);
+        int so[E];
+        half_slots<T, LOG_E>(st.rb, st.hb_in, so);
+        exchange_half<T, E>(x, lds, slot<T>(int(squeeze(uint32_t(t), st.hb_in))), lso,
+                            slot<T>(int(squeeze(et, st.hb_in))), so, st.hj_in, false);
     }
     for (int si = pass.stage_begin;;) {
         run_rounds<T, LOG_E>(x, st, rounds, ops, et, base);
         if (++si == pass.stage_end) break;
         const SStage nx = ldc<SStage>(stages + si);
-        uint32_t nt, nr[E];
-        stage_layout<LOG_E, LOG_T>(nx, nt, nr);
-        exchange_half<T, E>(x, lds, et, er, nt, nr, st.hb_out, st.hj_out, true);
+        uint32_t nt = 0;
+#pragma unroll
+        for (int j = 0; j < LOG_T; ++j) nt |= uint32_t((t >> j) & 1) << nx.tbits[j];
+        int wso[E], rso[E];
+        half_slots<T, LOG_E>(st.rb, st.hb_out, wso);
+        half_slots<T, LOG_E>(nx.rb, st.hb_out, rso);
+        exchange_half<T, E>(x, lds, slot<T>(int(squeeze(et, st.hb_out))), wso, slot<T>(int(squeeze(nt, st.hb_out))), rso,
+                            st.hj_out, true);
         st = nx;
         et = nt;
-#pragma unroll
-        for (int r = 0; r < E; ++r) er[r] = nr[r];
     }
     if (pass.direct & 2) {
         uint64_t gt = base;
@@ -726,7 +735,10 @@ __device__ __forceinline__ void run_block_half(T *__restrict__ a, const SPass &p
             st_nt(agw + v, x[r]);
         }
     } else {
-        exchange_half<T, E>(x, lds, et, er, uint32_t(t), lr, st.hb_out, st.hj_out, true);
+        int so[E];
+        half_slots<T, LOG_E>(st.rb, st.hb_out, so);
+        exchange_half<T, E>(x, lds, slot<T>(int(squeeze(et, st.hb_out))), so, slot<T>(int(squeeze(uint32_t(t), st.hb_out))),
+                            lso, st.hj_out, true);
         C *agw = reinterpret_cast<C *>(a) + (base | lane_part<LOG_T>(pass, t));
 #pragma unroll
         for (int k = 0; k < E; ++k) st_nt(agw + elem_part<LOG_E, LOG_T>(pass, k), x[k]);
