@@ -16,6 +16,7 @@
 // block goes through LDS once to change RB. LDS slots are padded (one slot per 2^P) so that the
 // usual RB/TB splits are free of bank conflicts.
 #include <algorithm>
+#include <functional>
 #include <utility>
 #include <array>
 #include <cstring>
@@ -58,6 +59,20 @@ __global__ __launch_bounds__(1 << LOG_T, MINW) void k_staged_half(T *__restrict_
     __shared__ C lds[lds_slots<T>(LOG_E + LOG_T - 1)];
     const SPass pass = ldc<SPass>(as_const(passp));
     run_block_half<T, LOG_E, LOG_T>(a, pass, blockIdx.x, as_const(stages), as_const(rounds), as_const(ops), lds);
+}
+
+// The half-buffer pass when every split is at a wave position: uniform split branches, and the block
+// fits in 128 VGPRs, so four 256-thread workgroups share a CU.
+template <typename T, int LOG_E, int LOG_T, int MINW>
+__global__ __launch_bounds__(1 << LOG_T, MINW) void k_staged_wave(T *__restrict__ a, const SPass *__restrict__ passp,
+                                                                  const SStage *__restrict__ stages,
+                                                                  const SRound *__restrict__ rounds,
+                                                                  const SOp *__restrict__ ops)
+{
+    using C = typename Vec<T>::C;
+    __shared__ C lds[lds_slots<T>(LOG_E + LOG_T - 1)];
+    const SPass pass = ldc<SPass>(as_const(passp));
+    run_block_wave<T, LOG_E, LOG_T>(a, pass, blockIdx.x, as_const(stages), as_const(rounds), as_const(ops), lds);
 }
 
 }  // namespace
@@ -507,9 +522,10 @@ static void emit_stage(SStage cur, uint32_t rbset, int log_e, int m, int dtype, 
 // Half-buffer form of a pass: for every LDS round trip (load layout -> first stage, stage -> next
 // stage, last stage -> store layout) pick a split bit that sits at the same thread position in both
 // layouts (in the load/store layout, local bit j is at thread position j), then pin those positions in
-// each stage's thread order. A split position >= 6 (a wave bit) gives each half whole wavefronts, and
-// a split bit >= 2P leaves the bank groups of the other bits unchanged, so those are preferred. Returns false (the pass keeps the full buffer) if a round trip has no such bit or the
-// pass ends a stage with a quantum swap.
+// each stage's thread order. Splits that are all at wave positions (>= 6: whole wavefronts per half)
+// select the wave-split kernel (SPass::direct bit 3); otherwise a split bit >= 2P, which leaves the bank
+// groups of the other bits unchanged, is preferred. Returns false (the pass keeps the full buffer) if a
+// round trip has no such bit or the pass ends a stage with a quantum swap.
 static bool assign_half(SPass &ps, std::vector<SStage> &stages, int m, int log_e, int dtype)
 {
     const int lt = m - log_e, P = dtype == QSIM_C128 ? 4 : 5;
@@ -525,39 +541,85 @@ static bool assign_half(SPass &ps, std::vector<SStage> &stages, int m, int log_e
         T[size_t(s)] = ((1u << m) - 1) & ~rb;
     }
     std::vector<int> bi(size_t(ns), -1), ji(size_t(ns), -1), bo(size_t(ns), -1), jo(size_t(ns), -1);
-    // best (b, j) with b in the candidate set `cand` (load/store: b == j), consistent with stage s's
-    // incoming split (one bit per position)
-    // (b, j) for the round trip out of stage s (s < 0: into stage 0 from the load layout), b in
-    // `cand`; in the load/store layout b == j. A position below P holds a low-run bit at its own
-    // position only (a stage that reads or writes memory directly keeps the low run on its first
-    // lanes in order); one bit per position within each stage.
-    auto pick = [&](int s, uint32_t cand, bool fixed_layout, int &b_out, int &j_out) {
-        int best = -1;
-        for (int j = 0; j < lt; ++j)
-            for (int b = 0; b < m; ++b) {
-                if (!((cand >> b) & 1) || (fixed_layout && b != j)) continue;
-                if ((j < P || b < P) && b != j) {
-                    // a low-run bit away from its own lane: only between stages that do not touch memory
-                    if (j < P) continue;
-                    if (s < 0 || (s == 0 && (ps.direct & 1)) || (s + 1 == ns - 1 && (ps.direct & 2)) || s == ns - 1) continue;
-                }
-                if (s >= 0 && ji[size_t(s)] >= 0 && ((j == ji[size_t(s)]) != (b == bi[size_t(s)]))) continue;
-                const int sc = (j >= 6 ? 10000 : 0) + (b >= 2 * P ? 1000 : 0) + (b >= P ? 500 : 0) + 32 * j + b;
-                if (sc > best) {
-                    best = sc;
-                    b_out = b;
-                    j_out = j;
-                }
-            }
-        return best >= 0;
+    // Round trip s leaves stage s (s = -1: the load into stage 0; s = ns - 1: the store). Its split
+    // (b, j) has b in cand_of(s); in the load/store layout b == j. A position below P holds a low-run
+    // bit at its own position only, and a low-run bit elsewhere only between stages that do not touch
+    // memory directly (those keep the low run on their first lanes in order), except the top one at a
+    // wave position. Within the stage it shares with the previous round trip, one bit per position.
+    auto needed = [&](int s) { return s < 0 ? !(ps.direct & 1) : s == ns - 1 ? !(ps.direct & 2) : true; };
+    auto cand_of = [&](int s) { return s < 0 ? T[0] : s == ns - 1 ? T[size_t(s)] : T[size_t(s)] & T[size_t(s + 1)]; };
+    auto valid = [&](int s, int b, int j, int in_b, int in_j) {
+        if (!((cand_of(s) >> b) & 1)) return false;
+        if ((s < 0 || s == ns - 1) && b != j) return false;
+        if ((j < P || b < P) && b != j) {
+            if (j < P) return false;
+            // next to a stage that touches memory directly, only the top low-run bit may move (to a
+            // wave position): its lanes then still cover 2^(P-1) consecutive amplitudes (128 bytes)
+            if (((s == 0 && (ps.direct & 1)) || (s + 1 == ns - 1 && (ps.direct & 2))) && (b != P - 1 || j < 6))
+                return false;
+        }
+        return in_j < 0 || ((j == in_j) == (b == in_b));
     };
-    if (!(ps.direct & 1) && !pick(-1, T[0], true, bi[0], ji[0])) return false;
-    for (int s = 0; s + 1 < ns; ++s) {
-        if (!pick(s, T[size_t(s)] & T[size_t(s + 1)], false, bo[size_t(s)], jo[size_t(s)])) return false;
-        bi[size_t(s + 1)] = bo[size_t(s)];
-        ji[size_t(s + 1)] = jo[size_t(s)];
+    // First look for splits that are all at wave positions (uniform halves: the 128-VGPR kernel), by a
+    // depth-first search along the chain of round trips, remembering failed states.
+    std::vector<int> wb(size_t(ns + 1), -1), wj(size_t(ns + 1), -1);
+    std::vector<char> failed(size_t((ns + 1) * (m + 1) * (lt + 1)), 0);
+    std::function<bool(int, int, int)> dfs = [&](int s, int in_b, int in_j) -> bool {
+        if (s == ns) return true;
+        char &f = failed[size_t(((s + 1) * (m + 1) + (in_b + 1)) * (lt + 1) + (in_j + 1))];
+        if (f) return false;
+        if (!needed(s)) {
+            wb[size_t(s + 1)] = wj[size_t(s + 1)] = -1;
+            if (dfs(s + 1, -1, -1)) return true;
+        } else {
+            for (int j = lt - 1; j >= 6; --j)
+                for (int b = m - 1; b >= 0; --b) {
+                    if (!valid(s, b, j, in_b, in_j)) continue;
+                    wb[size_t(s + 1)] = b;
+                    wj[size_t(s + 1)] = j;
+                    if (dfs(s + 1, b, j)) return true;
+                }
+        }
+        f = 1;
+        return false;
+    };
+    const bool wave = lt > 6 && dfs(-1, -1, -1);
+    if (wave) {
+        for (int s = -1; s < ns; ++s) {
+            if (s >= 0) {
+                bo[size_t(s)] = wb[size_t(s + 1)];
+                jo[size_t(s)] = wj[size_t(s + 1)];
+            }
+            if (s + 1 < ns) {
+                bi[size_t(s + 1)] = wb[size_t(s + 1)];
+                ji[size_t(s + 1)] = wj[size_t(s + 1)];
+            }
+        }
+    } else {
+        // otherwise the best split per round trip in order (a position >= 6 and a bit >= 2P preferred)
+        auto pick = [&](int s, int &b_out, int &j_out) {
+            const int in_b = s >= 0 ? bi[size_t(s)] : -1, in_j = s >= 0 ? ji[size_t(s)] : -1;
+            int best = -1;
+            for (int j = 0; j < lt; ++j)
+                for (int b = 0; b < m; ++b) {
+                    if (!valid(s, b, j, in_b, in_j)) continue;
+                    const int sc = (j >= 6 ? 10000 : 0) + (b >= 2 * P ? 1000 : 0) + (b >= P ? 500 : 0) + 32 * j + b;
+                    if (sc > best) {
+                        best = sc;
+                        b_out = b;
+                        j_out = j;
+                    }
+                }
+            return best >= 0;
+        };
+        if (needed(-1) && !pick(-1, bi[0], ji[0])) return false;
+        for (int s = 0; s + 1 < ns; ++s) {
+            if (!pick(s, bo[size_t(s)], jo[size_t(s)])) return false;
+            bi[size_t(s + 1)] = bo[size_t(s)];
+            ji[size_t(s + 1)] = jo[size_t(s)];
+        }
+        if (needed(ns - 1) && !pick(ns - 1, bo[size_t(ns - 1)], jo[size_t(ns - 1)])) return false;
     }
-    if (!(ps.direct & 2) && !pick(ns - 1, T[size_t(ns - 1)], true, bo[size_t(ns - 1)], jo[size_t(ns - 1)])) return false;
     for (int s = 0; s < ns; ++s) {
         SStage &st = stages[size_t(s0 + s)];
         int fj[2], fb[2], nf = 0;
@@ -575,7 +637,7 @@ static bool assign_half(SPass &ps, std::vector<SStage> &stages, int m, int log_e
         st.hb_out = uint8_t(std::max(bo[size_t(s)], 0));
         st.hj_out = uint8_t(std::max(jo[size_t(s)], 0));
     }
-    ps.direct |= 4;
+    ps.direct |= wave ? 12 : 4;
     return true;
 }
 
@@ -892,9 +954,22 @@ static void launch_half(StagedPlan *p, qsim_state *s, size_t i)
                        static_cast<T *>(s->data), p->d_passes + i, p->d_stages, p->d_rounds, p->d_ops);
 }
 
+template <typename T, int LE, int LT, int MW>
+static void launch_wave(StagedPlan *p, qsim_state *s, size_t i)
+{
+    hipLaunchKernelGGL((k_staged_wave<T, LE, LT, MW>), dim3(unsigned(dim(p->n - p->m))), dim3(1 << LT), 0, s->stream,
+                       static_cast<T *>(s->data), p->d_passes + i, p->d_stages, p->d_rounds, p->d_ops);
+}
+
 static int launch_pass(StagedPlan *p, qsim_state *s, size_t i)
 {
     const int v = p->log_e * 16 + p->log_t;
+    if ((p->passes[i].direct & 12) == 12 && p->dtype == QSIM_C128 && (v == 4 * 16 + 7 || v == 4 * 16 + 8)) {
+        if (v == 4 * 16 + 7) launch_wave<double, 4, 7, 4>(p, s, i);
+        else launch_wave<double, 4, 8, 4>(p, s, i);
+        QSIM_HIP(hipGetLastError());
+        return QSIM_OK;
+    }
     if (p->passes[i].direct & 4) {
         switch ((p->dtype == QSIM_C128 ? 256 : 0) + v) {
         case 256 + 4 * 16 + 6: launch_half<double, 4, 6, 3>(p, s, i); break;

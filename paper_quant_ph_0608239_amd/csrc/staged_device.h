@@ -72,7 +72,8 @@ struct SPass {
                         // last stage stores them straight to memory (no LDS round trip). Set when the
                         // stage's register bits avoid the low run, so that its thread bits keep
                         // consecutive lanes on consecutive amplitudes. Bit 2: every LDS round trip of
-                        // the pass has a split bit, and it runs with a half-size LDS buffer
+                        // the pass has a split bit, and it runs with a half-size LDS buffer. Bit 3: all
+                        // those split bits sit at wave positions (whole wavefronts per half)
     uint8_t R[16];      // physical bit of local bit s, ascending
 };
 
@@ -740,6 +741,129 @@ __device__ __forceinline__ void run_block_half(T *__restrict__ a, const SPass &p
         exchange_half<T, E>(x, lds, slot<T>(int(squeeze(et, st.hb_out))), so, slot<T>(int(squeeze(uint32_t(t), st.hb_out))),
                             lso, st.hj_out, true);
         C *agw = reinterpret_cast<C *>(a) + (base | lane_part<LOG_T>(pass, t));
+#pragma unroll
+        for (int k = 0; k < E; ++k) st_nt(agw + elem_part<LOG_E, LOG_T>(pass, k), x[k]);
+    }
+}
+
+// ---- wave-split half-buffer passes ----------------------------------------------------------------
+// The same round trips when every split position is a wave bit (j >= 6): each wavefront lies wholly in
+// one half, so the branches are uniform and each arm is straight-line code:
+//   first half:   [B0] write B1 read B2 B3
+//   second half:  [B0] B1 B2 write B3 read
+// Every wavefront passes the same barriers. The write half ends a stage and the read half starts the
+// next, so the amplitudes are not live across the stage loop; together with recomputing addresses and
+// thread bits where they are used, the block fits in 128 VGPRs (four 256-thread workgroups per CU).
+template <typename T, int E>
+__device__ __forceinline__ void wave_out(const typename Vec<T>::C *x, typename Vec<T>::C *lds, int wls, const int *wso,
+                                         uint32_t j, bool pre)
+{
+    const uint32_t second = __builtin_amdgcn_readfirstlane((uint32_t(threadIdx.x) >> j) & 1);
+    if (pre) __syncthreads();
+    if (second) {
+        __syncthreads();
+        __syncthreads();
+    }
+#pragma unroll
+    for (int r = 0; r < E; ++r) lds[wls + wso[r]] = x[r];
+    __syncthreads();
+}
+template <typename T, int E>
+__device__ __forceinline__ void wave_in(typename Vec<T>::C *x, const typename Vec<T>::C *lds, int rls, const int *rso,
+                                        uint32_t j)
+{
+    const uint32_t second = __builtin_amdgcn_readfirstlane((uint32_t(threadIdx.x) >> j) & 1);
+#pragma unroll
+    for (int r = 0; r < E; ++r) x[r] = lds[rls + rso[r]];
+    if (!second) {
+        __syncthreads();  // the other half may overwrite the buffer after this
+        __syncthreads();
+    }
+}
+
+// Process block `blk` of a wave-split pass (SPass::direct bits 2 and 3). `lds` holds
+// lds_slots<T>(LOG_E + LOG_T - 1) amplitudes.
+template <typename T, int LOG_E, int LOG_T>
+__device__ __forceinline__ void run_block_wave(T *__restrict__ a, const SPass &pass, uint64_t blk, cptr<SStage> stages,
+                                               cptr<SRound> rounds, cptr<SOp> ops, typename Vec<T>::C *lds)
+{
+    using C = typename Vec<T>::C;
+    constexpr int E = 1 << LOG_E;
+    const int t = threadIdx.x;
+    const uint64_t base = block_base<LOG_E + LOG_T>(pass, blk);
+    int lso[E];  // load/store layout: element k at local index k * 2^LOG_T + t, one place lower in the half
+#pragma unroll
+    for (int k = 0; k < E; ++k) lso[k] = slot<T>(k << (LOG_T - 1));
+    C x[E];
+    for (int si = pass.stage_begin; si < pass.stage_end; ++si) {
+        const SStage st = ldc<SStage>(stages + si);
+        const bool first = si == pass.stage_begin, last = si == pass.stage_end - 1;
+        int tt = t;
+        asm volatile("" : "+v"(tt));  // recompute the thread bits per stage rather than keep them live
+        uint32_t et = 0;
+#pragma unroll
+        for (int j = 0; j < LOG_T; ++j) et |= uint32_t((tt >> j) & 1) << st.tbits[j];
+        if (first && (pass.direct & 1)) {
+            uint64_t gt = base;
+#pragma unroll
+            for (int j = 0; j < LOG_T; ++j)
+                if ((t >> j) & 1) gt |= uint64_t(1) << st.ptb[j];
+            const C *ag = reinterpret_cast<const C *>(a) + gt;
+#pragma unroll
+            for (int r = 0; r < E; ++r) {
+                uint64_t v = 0;
+#pragma unroll
+                for (int j = 0; j < LOG_E; ++j)
+                    if ((r >> j) & 1) v |= uint64_t(1) << st.prb[j];
+                x[r] = ld_nt(ag + v);
+            }
+        } else {
+            if (first) {
+                uint64_t g0 = base | lane_part<LOG_T>(pass, t);
+                asm volatile("" : "+v"(g0));  // not kept alive until the store
+                const C *ag = reinterpret_cast<const C *>(a) + g0;
+#pragma unroll
+                for (int k = 0; k < E; ++k) x[k] = ld_nt(ag + elem_part<LOG_E, LOG_T>(pass, k));
+                wave_out<T, E>(x, lds, slot<T>(int(squeeze(uint32_t(t), st.hb_in))), lso, st.hj_in, false);
+            }
+            int so[E];
+            half_slots<T, LOG_E>(st.rb, st.hb_in, so);
+            wave_in<T, E>(x, lds, slot<T>(int(squeeze(et, st.hb_in))), so, st.hj_in);
+        }
+        run_rounds<T, LOG_E>(x, st, rounds, ops, et, base);
+        if (last) break;  // stored below, after the loop
+        int so[E];
+        half_slots<T, LOG_E>(st.rb, st.hb_out, so);
+        wave_out<T, E>(x, lds, slot<T>(int(squeeze(et, st.hb_out))), so, st.hj_out, true);
+    }
+    // storing after the stage loop keeps every load of the op tables ahead of the first store to the
+    // state (scalar loads stay legal)
+    const SStage st = ldc<SStage>(stages + (pass.stage_end - 1));
+    if (pass.direct & 2) {
+        uint64_t gt = base;
+#pragma unroll
+        for (int j = 0; j < LOG_T; ++j)
+            if ((t >> j) & 1) gt |= uint64_t(1) << st.ptb[j];
+        C *agw = reinterpret_cast<C *>(a) + gt;
+#pragma unroll
+        for (int r = 0; r < E; ++r) {
+            uint64_t v = 0;
+#pragma unroll
+            for (int j = 0; j < LOG_E; ++j)
+                if ((r >> j) & 1) v |= uint64_t(1) << st.prb[j];
+            st_nt(agw + v, x[r]);
+        }
+    } else {
+        uint32_t et = 0;
+#pragma unroll
+        for (int j = 0; j < LOG_T; ++j) et |= uint32_t((t >> j) & 1) << st.tbits[j];
+        int so[E];
+        half_slots<T, LOG_E>(st.rb, st.hb_out, so);
+        wave_out<T, E>(x, lds, slot<T>(int(squeeze(et, st.hb_out))), so, st.hj_out, true);
+        wave_in<T, E>(x, lds, slot<T>(int(squeeze(uint32_t(t), st.hb_out))), lso, st.hj_out);
+        uint64_t g0 = base | lane_part<LOG_T>(pass, t);
+        asm volatile("" : "+v"(g0));
+        C *agw = reinterpret_cast<C *>(a) + g0;
 #pragma unroll
         for (int k = 0; k < E; ++k) st_nt(agw + elem_part<LOG_E, LOG_T>(pass, k), x[k]);
     }
