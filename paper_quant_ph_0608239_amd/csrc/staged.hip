@@ -375,6 +375,7 @@ static void emit_stage(SStage cur, uint32_t rbset, int log_e, int m, int dtype, 
         const HOp &h = sops[xi];
         SOp o{};
         o.lt = -1;
+        o.alt_rank = -1;
         o.gcm = h.gcm;
         uint32_t rsel = 0;  // register part of the condition, over the register index r
         for (int s = 0; s < m; ++s)
@@ -394,7 +395,7 @@ static void emit_stage(SStage cur, uint32_t rbset, int log_e, int m, int dtype, 
             // through the conditional list (with an always-true condition)
             const bool rc = h.m[1] == 0.0 && h.m[5] == 0.0;
             const bool cond = o.lcm_t != 0 || rsel != 0 || o.gcm != 0 || !rc;
-            key[xi] = kLists * j + (cond ? 3 : 0);
+            key[xi] = kLists * j + (cond ? kListCond : 0);
         } else {
             const bool d0_one = h.angles == 1 || (h.angles == 0 && h.m[0] == 1.0 && h.m[1] == 0.0);
             const int lt = localof[h.target];
@@ -444,21 +445,23 @@ static void emit_stage(SStage cur, uint32_t rbset, int log_e, int m, int dtype, 
         const int lo = localof[qo];
         SOp &o = rec[d];
         o.alt_col = col ? 1u : 0u;
+        o.alt_rank = -1;
         if (lo >= 0 && ((rbset >> lo) & 1)) {
             const int jo = rank_of(lo);
+            o.alt_rank = jo;
             for (int p = 0; p < E / 2; ++p) {
                 const int r = (p & ((1 << j) - 1)) | ((p >> j) << (j + 1));
                 if ((r >> jo) & 1) o.amask |= 1u << p;
             }
-            key[d] = kLists * j + 1;
+            key[d] = kLists * j + kListPairFlip + (jo < j ? jo : jo - 1);
         } else if (lo >= 0) {
             o.amask = (1u << (E / 2)) - 1;
             o.alt_lcm = 1u << lo;
-            key[d] = kLists * j + 2;
+            key[d] = kLists * j + kListLaneFlip;
         } else {
             o.amask = (1u << (E / 2)) - 1;
             o.galt = other;
-            key[d] = kLists * j + 1;
+            key[d] = kLists * j + kListBlockFlip;
         }
     };
     // the only dense op of its round on its register bit

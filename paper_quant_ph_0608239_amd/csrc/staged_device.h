@@ -33,17 +33,19 @@ struct SOp {
     uint32_t amask;
     uint32_t alt_lcm;
     uint32_t alt_col;
-    uint32_t pad;
+    int32_t alt_rank;  // flip chosen per pair: the rank of the other qubit's register bit, else -1
 };
 
-// A round of a stage. For register bit j, four lists of dense ops (the first three hold 2x2s with a
-// real first column only): [seg[4j], seg[4j+1]) without condition, [seg[4j+1], seg[4j+2]) without condition but with a fused flip chosen per pair or per
-// block, [seg[4j+2], seg[4j+3]) with a fused flip chosen per lane, [seg[4j+3], seg[4j+4]) with a
-// condition. Then the sign flips (diagonal ops whose only factor is -1) [seg[4 LOG_E],
-// seg[4 LOG_E + 1]) and the other diagonal ops [seg[4 LOG_E + 1], seg[4 LOG_E + 2]). Dense ops of
-// one round on different bits commute, diagonal ops commute with each other, and every diagonal op
-// of the round runs after its dense ops, so this order equals circuit order.
-constexpr int kLists = 4;
+// A round of a stage. For register bit j, eight lists of dense ops [seg[8j + l], seg[8j + l + 1]): l = 0
+// without condition; l = 1 with a sign flip fused per block; l = 2 + i with a flip fused per pair, by
+// the i-th other register bit (i < LOG_E - 1); l = 6 with a flip fused per lane; l = 7 with a
+// condition. The first seven hold 2x2s with a real first column only. Then the sign flips (diagonal
+// ops whose only factor is -1) [seg[8 LOG_E], seg[8 LOG_E + 1]) and the other diagonal ops
+// [seg[8 LOG_E + 1], seg[8 LOG_E + 2]). Dense ops of one round on different bits commute, diagonal ops
+// commute with each other, and every diagonal op of the round runs after its dense ops, so this order
+// equals circuit order.
+constexpr int kLists = 8;
+constexpr int kListBlockFlip = 1, kListPairFlip = 2, kListLaneFlip = 6, kListCond = 7;
 struct SRound {
     int32_t seg[kLists * kMaxLogE + 4];
 };
@@ -226,16 +228,16 @@ __device__ __forceinline__ void xor_sign(double &v, uint32_t t)
 }
 __device__ __forceinline__ void xor_sign(float &v, uint32_t t) { v = __builtin_bit_cast(float, __builtin_bit_cast(uint32_t, v) ^ t); }
 
-// A dense op with a fused flip chosen per pair (register bits) or per block: in the pairs that take
-// it, the second amplitude changes sign before the 2x2 (column flip) or after it (row flip). Those
-// pairs use the 2x2 with column 1 or row 1 negated instead; the choice between the two coefficient
-// sets is wave-uniform (scalar selects), so the pair costs the same FMAs as an unconditional one.
-// Negating coefficients gives the same bits as negating the data (rounding is sign-symmetric).
-template <typename T, int E, int RB>
-__device__ __forceinline__ void op_dense_alt_uniform(typename Vec<T>::C *x, const SOp &op, uint64_t base)
+// Dense ops with a fused flip chosen per pair (register bits) or per block: in the pairs that take it,
+// the second amplitude changes sign before the 2x2 (column flip) or after it (row flip). Those pairs
+// use the 2x2 with column 1 or row 1 negated instead, which gives the same bits as negating the data
+// (rounding is sign-symmetric). Per block, the coefficient set is chosen once per op; per pair, the
+// pairs that flip are those with register bit K set, and each list holds one K, so every pair's set
+// is fixed at compile time. Either way the op costs the same FMAs as an unconditional one.
+template <typename T>
+__device__ __forceinline__ void flip_coefs(const SOp &op, U2<T> &u, U2<T> &v)
 {
     const T *c = coef<T>(op);
-    U2<T> u, v;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         u.r[k] = c[2 * k];
@@ -248,20 +250,30 @@ __device__ __forceinline__ void op_dense_alt_uniform(typename Vec<T>::C *x, cons
     v.r[2] = col ? u.r[2] : -u.r[2];
     v.r[3] = -u.r[3];
     v.i[3] = -u.i[3];
-    const uint32_t am = (base & op.galt) == op.galt ? op.amask : 0u;
+}
+template <typename T, int E, int RB>
+__device__ __forceinline__ void op_dense_flip_block(typename Vec<T>::C *x, const SOp &op, uint64_t base)
+{
+    U2<T> u, v, w;
+    flip_coefs<T>(op, u, v);
+    const bool neg = (base & op.galt) == op.galt;
 #pragma unroll
-    for (int r = 0; r < E; ++r) {
-        if ((r >> RB) & 1) continue;
-        const int p = (r & ((1 << RB) - 1)) | ((r >> (RB + 1)) << RB);
-        const bool neg = (am >> p) & 1;
-        U2<T> w;
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            w.r[k] = neg ? v.r[k] : u.r[k];
-            w.i[k] = neg ? v.i[k] : u.i[k];
-        }
-        pair2x2_rc<T, true>(x[r], x[r | (1 << RB)], w);
+    for (int q = 0; q < 4; ++q) {
+        w.r[q] = neg ? v.r[q] : u.r[q];
+        w.i[q] = neg ? v.i[q] : u.i[q];
     }
+#pragma unroll
+    for (int r = 0; r < E; ++r)
+        if (!((r >> RB) & 1)) pair2x2_rc<T, true>(x[r], x[r | (1 << RB)], w);
+}
+template <typename T, int E, int RB, int K>
+__device__ __forceinline__ void op_dense_flip_pair(typename Vec<T>::C *x, const SOp &op)
+{
+    U2<T> u, v;
+    flip_coefs<T>(op, u, v);
+#pragma unroll
+    for (int r = 0; r < E; ++r)
+        if (!((r >> RB) & 1)) pair2x2_rc<T, true>(x[r], x[r | (1 << RB)], ((r >> K) & 1) ? v : u);
 }
 
 // A dense op with a fused flip chosen per lane (a thread bit): every pair of the lanes that take it
@@ -358,6 +370,21 @@ __device__ __forceinline__ void op_flip(typename Vec<T>::C *x, const SOp &op, ui
     }
 }
 
+// the i-th register bit other than J
+constexpr int other_bit(int J, int i) { return i < J ? i : i + 1; }
+
+// the per-pair flip list i of register bit J (flips by register bit other_bit(J, i))
+template <typename T, int E, int J, int I>
+__device__ __forceinline__ void pair_flip_list(typename Vec<T>::C *x, const SRound &rd, cptr<SOp> ops)
+{
+    if constexpr ((1 << (I + 1)) < E) {
+        for (int oi = rd.seg[kLists * J + kListPairFlip + I]; oi < rd.seg[kLists * J + kListPairFlip + I + 1]; ++oi) {
+            const SOp op = ldc<SOp>(ops + oi);
+            op_dense_flip_pair<T, E, J, other_bit(J, I)>(x, op);
+        }
+    }
+}
+
 // the ops of one round on register bit J
 template <typename T, int E, int J>
 __device__ __forceinline__ void round_bit(typename Vec<T>::C *x, const SRound &rd, cptr<SOp> ops, uint32_t et,
@@ -367,15 +394,19 @@ __device__ __forceinline__ void round_bit(typename Vec<T>::C *x, const SRound &r
         const SOp op = ldc<SOp>(ops + oi);
         op_dense_all<T, E, J>(x, op);
     }
-    for (int oi = rd.seg[kLists * J + 1]; oi < rd.seg[kLists * J + 2]; ++oi) {
+    for (int oi = rd.seg[kLists * J + kListBlockFlip]; oi < rd.seg[kLists * J + kListBlockFlip + 1]; ++oi) {
         const SOp op = ldc<SOp>(ops + oi);
-        op_dense_alt_uniform<T, E, J>(x, op, base);
+        op_dense_flip_block<T, E, J>(x, op, base);
     }
-    for (int oi = rd.seg[kLists * J + 2]; oi < rd.seg[kLists * J + 3]; ++oi) {
+    pair_flip_list<T, E, J, 0>(x, rd, ops);
+    pair_flip_list<T, E, J, 1>(x, rd, ops);
+    pair_flip_list<T, E, J, 2>(x, rd, ops);
+    pair_flip_list<T, E, J, 3>(x, rd, ops);
+    for (int oi = rd.seg[kLists * J + kListLaneFlip]; oi < rd.seg[kLists * J + kListLaneFlip + 1]; ++oi) {
         const SOp op = ldc<SOp>(ops + oi);
         op_dense_alt_lane<T, E, J>(x, op, et, base);
     }
-    for (int oi = rd.seg[kLists * J + 3]; oi < rd.seg[kLists * J + 4]; ++oi) {
+    for (int oi = rd.seg[kLists * J + kListCond]; oi < rd.seg[kLists * J + kListCond + 1]; ++oi) {
         const SOp op = ldc<SOp>(ops + oi);
         if ((base & op.gcm) != op.gcm) continue;  // a control outside R is 0 in this block
         op_dense_cond<T, E, J>(x, op, (et & op.lcm_t) == op.lcm_t);
