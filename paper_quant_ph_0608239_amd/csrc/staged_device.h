@@ -390,18 +390,22 @@ template <typename T, int E, int J>
 __device__ __forceinline__ void round_bit(typename Vec<T>::C *x, const SRound &rd, cptr<SOp> ops, uint32_t et,
                                           uint64_t base)
 {
+    // one test skips all lists of a bit without dense ops in this round, one more the flip lists
+    if (rd.seg[kLists * J] == rd.seg[kLists * J + kLists]) return;
     for (int oi = rd.seg[kLists * J]; oi < rd.seg[kLists * J + 1]; ++oi) {
         const SOp op = ldc<SOp>(ops + oi);
         op_dense_all<T, E, J>(x, op);
     }
-    for (int oi = rd.seg[kLists * J + kListBlockFlip]; oi < rd.seg[kLists * J + kListBlockFlip + 1]; ++oi) {
-        const SOp op = ldc<SOp>(ops + oi);
-        op_dense_flip_block<T, E, J>(x, op, base);
+    if (rd.seg[kLists * J + kListBlockFlip] != rd.seg[kLists * J + kListLaneFlip]) {
+        for (int oi = rd.seg[kLists * J + kListBlockFlip]; oi < rd.seg[kLists * J + kListBlockFlip + 1]; ++oi) {
+            const SOp op = ldc<SOp>(ops + oi);
+            op_dense_flip_block<T, E, J>(x, op, base);
+        }
+        pair_flip_list<T, E, J, 0>(x, rd, ops);
+        pair_flip_list<T, E, J, 1>(x, rd, ops);
+        pair_flip_list<T, E, J, 2>(x, rd, ops);
+        pair_flip_list<T, E, J, 3>(x, rd, ops);
     }
-    pair_flip_list<T, E, J, 0>(x, rd, ops);
-    pair_flip_list<T, E, J, 1>(x, rd, ops);
-    pair_flip_list<T, E, J, 2>(x, rd, ops);
-    pair_flip_list<T, E, J, 3>(x, rd, ops);
     for (int oi = rd.seg[kLists * J + kListLaneFlip]; oi < rd.seg[kLists * J + kListLaneFlip + 1]; ++oi) {
         const SOp op = ldc<SOp>(ops + oi);
         op_dense_alt_lane<T, E, J>(x, op, et, base);
