@@ -329,7 +329,7 @@ def main() -> int:
     if args.seed is None:
         args.seed = 31 if args.dtype == "c64" else 21
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path (no sharding, no "
+        print("bench.py runs on one GPU only: the library has no multi-GPU path (no sharding, no "
               "collectives); run it with --gpus 1.", file=sys.stderr)
         return 2
 

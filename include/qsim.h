@@ -43,7 +43,7 @@ enum {
     QSIM_EINVAL = -1,      /* bad argument (range, null pointer, size mismatch, duplicate qubit) */
     QSIM_ENOMEM = -2,      /* device allocation failed or the state does not fit */
     QSIM_EDEVICE = -3,     /* a HIP runtime error; text in qsim_last_error() */
-    QSIM_EUNSUPPORTED = -4 /* valid request that this build does not support */
+    QSIM_EUNSUPPORTED = -4 /* valid request that the library does not support */
 };
 
 #define QSIM_MAX_QUBITS 40 /* index arithmetic limit; memory is the practical limit (34 c64 / 33 c128) */

@@ -25,7 +25,7 @@ def L():
     return _lib.lib()
 
 
-def test_header_declares_the_north_star_calls():
+def test_header_declares_the_core_calls():
     names = declared_functions()
     for must in ["qsim_alloc", "qsim_apply_1q", "qsim_apply_ctrl", "qsim_apply_fused", "qsim_probs", "qsim_norm"]:
         assert must in names
