@@ -1,0 +1,47 @@
+// Test helper (host only): run the staged scheduler of libqsim on a gate list and write its tables, so
+// that a CPU test can check them. Usage: sched_dump <gates.bin> <n> <dtype> <m> <log_e> <out.bin>.
+// gates.bin holds qsim_gate records; out.bin holds the four record sizes, the four table lengths and
+// the pass, stage, round and op tables.
+#include <cstdint>
+#include <cstdio>
+#include <cstdlib>
+#include <vector>
+
+#include "staged_device.h"
+
+using namespace qsim::staged;
+
+int main(int argc, char **argv)
+{
+    if (argc != 7) {
+        std::fprintf(stderr, "usage: sched_dump gates.bin n dtype m log_e out.bin\n");
+        return 2;
+    }
+    std::FILE *f = std::fopen(argv[1], "rb");
+    if (!f) return 2;
+    std::vector<qsim_gate> gates;
+    qsim_gate g;
+    while (std::fread(&g, sizeof g, 1, f) == 1) gates.push_back(g);
+    std::fclose(f);
+    std::vector<SPass> passes;
+    std::vector<SStage> stages;
+    std::vector<SRound> rounds;
+    std::vector<SOp> ops;
+    const int rc = staged_schedule(std::atoi(argv[2]), std::atoi(argv[3]), std::atoi(argv[4]), std::atoi(argv[5]), gates,
+                                   passes, stages, rounds, ops);
+    if (rc) {
+        std::printf("rc=%d\n", rc);
+        return 1;
+    }
+    std::FILE *o = std::fopen(argv[6], "wb");
+    if (!o) return 2;
+    const uint64_t head[8] = {sizeof(SPass), sizeof(SStage), sizeof(SRound), sizeof(SOp),
+                              passes.size(), stages.size(), rounds.size(), ops.size()};
+    std::fwrite(head, sizeof head, 1, o);
+    std::fwrite(passes.data(), sizeof(SPass), passes.size(), o);
+    std::fwrite(stages.data(), sizeof(SStage), stages.size(), o);
+    std::fwrite(rounds.data(), sizeof(SRound), rounds.size(), o);
+    std::fwrite(ops.data(), sizeof(SOp), ops.size(), o);
+    std::fclose(o);
+    return 0;
+}

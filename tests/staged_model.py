@@ -1,0 +1,219 @@
+"""Test infrastructure: a numpy model of the LDS-staged schedule tables (the records that the staged
+kernels read), used by the CPU tests of the scheduler.
+
+* `load_tables` reads what tests/sched_dump.cpp writes (the host scheduler's output).
+* `run_schedule` applies the tables to a state by global index: per pass and block, per stage the
+  register/thread layout, per round the op lists in the kernels' order with their conditions, fused
+  flips and diagonal factors, and the stage-end swap. Comparing it with the oracle checks the
+  scheduler's decomposition without a GPU.
+* `check_half_exchanges` simulates, slot by slot, every LDS round trip of a half-buffer pass (two
+  halves split by a bit at the same thread position in both layouts; slots with the split bit
+  squeezed out and one pad slot per 2^P) and checks that no two elements share a slot and every read
+  returns the element the next layout expects.
+"""
+import numpy as np
+
+KL = 8  # op lists per register bit: 0 plain, 1 block flip, 2..5 pair flips, 6 lane flip, 7 condition
+PASS = np.dtype([('m', '<i4'), ('sb', '<i4'), ('se', '<i4'), ('direct', '<i4'), ('R', 'u1', 16)])
+STAGE = np.dtype([('rb0', '<i4'), ('rb1', '<i4'), ('rb', 'u1', 8), ('tb', 'u1', 16), ('sp', '<i4'), ('sq', '<i4'),
+                  ('slcm', '<u4'), ('hb_in', 'u1'), ('hj_in', 'u1'), ('hb_out', 'u1'), ('hj_out', 'u1'),
+                  ('sgcm', '<u8'), ('prb', 'u1', 8), ('ptb', 'u1', 16)])
+ROUND = np.dtype([('seg', '<i4', KL * 5 + 4)])
+OP = np.dtype([('pmask', '<u4'), ('lcm_t', '<u4'), ('gcm', '<u8'), ('gtb', '<u8'), ('m0', '<u4'), ('m1', '<u4'),
+               ('lt', '<i4'), ('angles', '<i4'), ('m', '<f8', 8), ('theta', '<f8', 2), ('mf', '<f4', 8), ('galt', '<u8'),
+               ('amask', '<u4'), ('alt_lcm', '<u4'), ('alt_col', '<u4'), ('alt_rank', '<i4')])
+
+
+def load_tables(path):
+    b = open(path, 'rb').read()
+    head = np.frombuffer(b[:64], '<u8')
+    sizes, counts = [int(v) for v in head[:4]], [int(v) for v in head[4:]]
+    assert sizes == [PASS.itemsize, STAGE.itemsize, ROUND.itemsize, OP.itemsize], sizes
+    off, out = 64, []
+    for dt, c in zip((PASS, STAGE, ROUND, OP), counts):
+        out.append(np.frombuffer(b, dt, c, off).copy())
+        off += dt.itemsize * c
+    P, S, RD, O = out
+    for o in O:  # factors of angle-defined diagonal ops, as the device fills them in
+        if o['angles'] == 1:
+            o['m'][0:4] = [1.0, 0.0, np.cos(o['theta'][0]), np.sin(o['theta'][0])]
+        elif o['angles'] == 2:
+            o['m'][0:4] = [np.cos(o['theta'][0]), np.sin(o['theta'][0]), np.cos(o['theta'][1]), np.sin(o['theta'][1])]
+    return P, S, RD, O
+
+
+def _layout(st, m, le):
+    lt = m - le
+    t = np.arange(1 << lt)
+    et = np.zeros(1 << lt, dtype=np.int64)
+    for j in range(lt):
+        et |= ((t >> j) & 1) << int(st['tb'][j])
+    er = np.zeros(1 << le, dtype=np.int64)
+    for r in range(1 << le):
+        for j in range(le):
+            if (r >> j) & 1:
+                er[r] |= 1 << int(st['rb'][j])
+    return et, er
+
+
+def _apply_dense(X, op, j, le, et, base, kind, flip_bit):
+    """One dense op on register bit j. kind: 'plain', 'flip' (block/pair/lane fused flip), 'cond'."""
+    mm = op['m']
+    u = np.array([[mm[0] + 1j * mm[1], mm[2] + 1j * mm[3]], [mm[4] + 1j * mm[5], mm[6] + 1j * mm[7]]])
+    if kind != 'cond':  # those lists hold 2x2s with a real first column; the kernels do not read u00/u10 im
+        u[0, 0], u[1, 0] = mm[0], mm[4]
+    if kind == 'cond' and (base & int(op['gcm'])) != int(op['gcm']):
+        return
+    lane_ok = (et & int(op['lcm_t'])) == int(op['lcm_t']) if kind == 'cond' else np.ones(len(et), bool)
+    for r in range(1 << le):
+        if (r >> j) & 1:
+            continue
+        p = (r & ((1 << j) - 1)) | ((r >> (j + 1)) << j)
+        if kind == 'cond' and not (int(op['pmask']) >> p) & 1:
+            continue
+        r1 = r | (1 << j)
+        a0, a1 = X[:, r].copy(), X[:, r1].copy()
+        n0 = u[0, 0] * a0 + u[0, 1] * a1
+        n1 = u[1, 0] * a0 + u[1, 1] * a1
+        if kind == 'flip':
+            if flip_bit is not None:  # per pair: the pairs with register bit flip_bit set
+                neg = np.full(len(et), bool((r >> flip_bit) & 1))
+            else:
+                blk_ok = (base & int(op['galt'])) == int(op['galt'])
+                neg = np.full(len(et), blk_ok and bool((int(op['amask']) >> p) & 1))
+                neg &= (et & int(op['alt_lcm'])) == int(op['alt_lcm'])
+            if op['alt_col']:
+                n0 = np.where(neg, u[0, 0] * a0 - u[0, 1] * a1, n0)
+                n1 = np.where(neg, u[1, 0] * a0 - u[1, 1] * a1, n1)
+            else:
+                n1 = np.where(neg, -n1, n1)
+        X[:, r] = np.where(lane_ok, n0, a0)
+        X[:, r1] = np.where(lane_ok, n1, a1)
+
+
+def run_schedule(psi, n, m, le, P, S, RD, O):
+    psi = psi.copy()
+    for ps in P:
+        R = [int(v) for v in ps['R'][:m]]
+        nonres = [q for q in range(n) if q not in R]
+        e = np.arange(1 << m)
+        loc = np.zeros(1 << m, dtype=np.int64)
+        for s_, q in enumerate(R):
+            loc |= ((e >> s_) & 1) << q
+        for b in range(1 << (n - m)):
+            base = 0
+            for k, q in enumerate(nonres):
+                base |= ((b >> k) & 1) << q
+            idx = base | loc
+            blk = psi[idx].copy()
+            for si in range(ps['sb'], ps['se']):
+                st = S[si]
+                et, er = _layout(st, m, le)
+                X = blk[et[:, None] | er[None, :]].copy()
+                for ri in range(st['rb0'], st['rb1']):
+                    seg = RD[ri]['seg']
+                    for j in range(le):
+                        for lst in range(KL):
+                            for oi in range(seg[KL * j + lst], seg[KL * j + lst + 1]):
+                                op = O[oi]
+                                if lst == 0:
+                                    _apply_dense(X, op, j, le, et, base, 'plain', None)
+                                elif lst == KL - 1:
+                                    _apply_dense(X, op, j, le, et, base, 'cond', None)
+                                elif 2 <= lst <= 5:
+                                    i = lst - 2
+                                    kb = i if i < j else i + 1
+                                    assert int(op['alt_rank']) == kb
+                                    _apply_dense(X, op, j, le, et, base, 'flip', kb)
+                                else:
+                                    _apply_dense(X, op, j, le, et, base, 'flip', None)
+                    for oi in range(seg[KL * le], seg[KL * le + 2]):  # sign flips, then other diagonal ops
+                        op = O[oi]
+                        if (base & int(op['gcm'])) != int(op['gcm']):
+                            continue
+                        mm = op['m']
+                        d0, d1 = mm[0] + 1j * mm[1], mm[2] + 1j * mm[3]
+                        lane_ok = (et & int(op['lcm_t'])) == int(op['lcm_t'])
+                        f0 = np.full(len(et), d0)
+                        f1 = np.full(len(et), d1)
+                        if op['lt'] >= 0:
+                            f1 = np.where(((et >> int(op['lt'])) & 1) == 1, d1, d0)
+                        elif op['gtb']:
+                            f1 = np.full(len(et), d1 if (base & int(op['gtb'])) else d0)
+                        f0 = np.where(lane_ok, f0, 1)
+                        f1 = np.where(lane_ok, f1, 1)
+                        for r in range(1 << le):
+                            if (int(op['m1']) >> r) & 1:
+                                X[:, r] *= f1
+                            if (int(op['m0']) >> r) & 1:
+                                X[:, r] *= f0
+                d = et[:, None] | er[None, :]
+                if st['sp'] >= 0 and (base & int(st['sgcm'])) == int(st['sgcm']):
+                    p_, q_ = int(st['sp']), int(st['sq'])
+                    sel = ((d & int(st['slcm'])) == int(st['slcm'])) & ((((d >> p_) ^ (d >> q_)) & 1) == 1)
+                    d = np.where(sel, d ^ ((1 << p_) | (1 << q_)), d)
+                blk[d] = X
+            psi[idx] = blk
+    return psi
+
+
+def _slot(e, P):
+    return e + (e >> P)
+
+
+def _squeeze(v, b):
+    low = (1 << b) - 1
+    return (v & low) | ((v >> 1) & ~low)
+
+
+def _exchange(A, B, b, j, m, le, P):
+    lt = m - le
+    t = np.arange(1 << lt)
+    nslots = (1 << (m - 1)) + ((1 << (m - 1)) >> P)
+    mine = (t >> j) & 1
+    for half in (0, 1):
+        buf = np.full(nslots, -1, dtype=np.int64)
+        th = t[mine == half]
+        w_idx = A[0][th][:, None] | A[1][None, :]
+        w_slot = _slot(_squeeze(A[0][th], b), P)[:, None] + _slot(_squeeze(A[1], b), P)[None, :]
+        assert (((w_idx >> b) & 1) == half).all(), 'an element outside its half'
+        assert 0 <= w_slot.min() and w_slot.max() < nslots, 'slot out of range'
+        assert len(np.unique(w_slot)) == w_slot.size, 'two elements in one slot'
+        buf[w_slot.ravel()] = w_idx.ravel()
+        r_idx = B[0][th][:, None] | B[1][None, :]
+        r_slot = _slot(_squeeze(B[0][th], b), P)[:, None] + _slot(_squeeze(B[1], b), P)[None, :]
+        assert r_slot.max() < nslots, 'read slot out of range'
+        assert (buf[r_slot] == r_idx).all(), 'a read returned the wrong element'
+
+
+def check_half_exchanges(P, S, m, le, c128):
+    """Returns (passes with a half-size buffer, those with wave-level splits)."""
+    Pb = 4 if c128 else 5
+    lt = m - le
+    t = np.arange(1 << lt, dtype=np.int64)
+    load = (t, np.arange(1 << le, dtype=np.int64) << lt)
+    nhalf = nwave = 0
+    for ps in P:
+        if not ps['direct'] & 4:
+            continue
+        nhalf += 1
+        sts = [S[i] for i in range(ps['sb'], ps['se'])]
+        js = []
+        for st in sts:
+            rb = set(int(x) for x in st['rb'][:le])
+            assert sorted(int(x) for x in st['tb'][:lt]) == sorted(set(range(m)) - rb)
+        lays = [_layout(st, m, le) for st in sts]
+        if not ps['direct'] & 1:
+            _exchange(load, lays[0], int(sts[0]['hb_in']), int(sts[0]['hj_in']), m, le, Pb)
+            js.append(int(sts[0]['hj_in']))
+        for k in range(len(sts) - 1):
+            assert sts[k]['hb_out'] == sts[k + 1]['hb_in'] and sts[k]['hj_out'] == sts[k + 1]['hj_in']
+            _exchange(lays[k], lays[k + 1], int(sts[k]['hb_out']), int(sts[k]['hj_out']), m, le, Pb)
+            js.append(int(sts[k]['hj_out']))
+        if not ps['direct'] & 2:
+            _exchange(lays[-1], load, int(sts[-1]['hb_out']), int(sts[-1]['hj_out']), m, le, Pb)
+            js.append(int(sts[-1]['hj_out']))
+        if ps['direct'] & 8:
+            assert all(j >= 6 for j in js), 'a wave-split pass with a lane-level split'
+            nwave += 1
+    return nhalf, nwave
