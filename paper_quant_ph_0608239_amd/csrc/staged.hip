@@ -973,6 +973,12 @@ static int launch_pass(StagedPlan *p, qsim_state *s, size_t i)
         QSIM_HIP(hipGetLastError());
         return QSIM_OK;
     }
+    if ((p->passes[i].direct & 12) == 12 && p->dtype == QSIM_C64 && (v == 5 * 16 + 7 || v == 5 * 16 + 8)) {
+        if (v == 5 * 16 + 7) launch_wave<float, 5, 7, 4>(p, s, i);
+        else launch_wave<float, 5, 8, 4>(p, s, i);
+        QSIM_HIP(hipGetLastError());
+        return QSIM_OK;
+    }
     if (p->passes[i].direct & 4) {
         switch ((p->dtype == QSIM_C128 ? 256 : 0) + v) {
         case 256 + 4 * 16 + 6: launch_half<double, 4, 6, 3>(p, s, i); break;
