@@ -2,13 +2,15 @@
 
 Default workload: the 33-qubit complex128 brickwork circuit (128 GiB state, 20 layers of Haar-random
 2x2 unitaries on every qubit + CZ on alternating neighbour pairs, 980 gates, seed 21, start
-|0...0>). A step is one full run of the circuit from |0...0> through the framework's fastest plan;
-the plain per-gate plan (one sweep per gate) is timed once beside it.
+|0...0>). A step is one full run of the circuit from |0...0> through the framework's fastest plan
+(the initial state is generated inside the first pass); the plain per-gate plan (one sweep per gate)
+and the fused plan (5-qubit dense blocks on the FP64 matrix cores) are each timed whole beside it.
 
 Prints ONE JSON line (rank 0). `value` is gates/s of the whole job (one GPU) with the state already
 resident in HBM. `roofline` describes the dominant kernel of the timed plan, its average launch
 duration measured with HIP events on the state's stream over the timed steps. `cpu_baseline` is the
-FP64 CPU oracle timed on a bounded sample of the same circuit family on this host's cores.
+FP64 CPU oracle run on whole circuits of the same family at sizes it finishes in seconds (28 qubits
+on all host threads, 20 qubits on one), measured, with the GPU timed on the same 28-qubit circuit.
 """
 from __future__ import annotations
 
@@ -26,9 +28,12 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBPS = 8000.0
 FP64_PEAK_TFLOPS = 78.6       # dense FP64 MFMA
 FP32_MFMA_PEAK_TFLOPS = 157.3  # dense FP32 MFMA
-# vector ALU: 256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA) x 2.4 GHz = 78.6 TFLOP/s, the same for FP64 and
-# for FP32 as compiled here (no packed FP32 instructions)
-VALU_PEAK_TFLOPS = 78.6
+# vector ALU, published: FP64 78.6 TFLOP/s = 256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA) x 2.4 GHz;
+# FP32 157.3 TFLOP/s, which needs packed (two-wide) FP32 instructions
+FP64_VALU_PEAK_TFLOPS = 78.6
+FP32_VALU_PEAK_TFLOPS = 157.3
+# the FP32 rate without packed instructions (the code here is compiled without them)
+FP32_UNPACKED_PEAK_TFLOPS = 78.6
 METRIC = "gates/s & effective HBM GB/s (% of peak) at 30–34 qubits; fused vs plain"
 
 
@@ -68,30 +73,76 @@ def load_traffic(workload: str, kernel: str):
     return e.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(n_full: int, layers: int, seed: int, budget_s: float, n_sample: int) -> dict:
-    """The oracle (unmodified) on the same brickwork family at n_sample qubits, gates in circuit order
-    until the time budget is spent; gates/s scaled to n_full by the paper's O(2^L) work per gate."""
+def _oracle_run_json(n: int, layers: int, seed: int):
+    """Whole-circuit oracle run of the brickwork family in this process (its OpenMP threads as the
+    environment sets them); wall time around the gate loop only."""
     import oracle
     import qsim_workloads as wl
     oracle.lib()
-    text = wl.brickwork_circuit(n_sample, layers, seed)
-    c = oracle.parse(text)
-    a = oracle.basis_state(c.n, 0)
+    text = wl.brickwork_circuit(n, layers, seed)
+    psi, secs, gates = oracle.timed_run(text)
+    return {"n": n, "gates": gates, "seconds": secs, "threads": oracle.threads()}, psi
+
+
+def cpu_baseline(args, popts: dict, dtype: str) -> dict:
+    """The oracle, unmodified, on whole circuits of the benchmark's family at sizes it finishes in
+    seconds: on every host thread at args.cpu_n qubits (the GPU plan is timed on the same circuit in
+    the same run and checked against the oracle's state), and on one thread at args.cpu_n1 qubits.
+    Rates are the measured ones, with no scaling to other sizes."""
+    import subprocess
+
+    import numpy as np
+    import torch
+
+    import paper_quant_ph_0608239_amd as q
+    import qsim_workloads as wl
+    n, layers, seed = args.cpu_n, args.layers, args.seed
+    full, psi = _oracle_run_json(n, layers, seed)
+    circ = q.parse_circuit(wl.brickwork_circuit(n, layers, seed))
+    plain = q.Plan(circ, "c128", method="plain")
+    alg_bytes = plain.info["alg_bytes"]  # the per-gate sweeps the oracle performs, in bytes moved
+    plain.close()
+    # the same circuit on the GPU, through the benchmark's plan options (complex128 at this size)
+    gpu = {}
+    s = q.State(n, "c128")
+    opts = dict(popts)
+    if opts["method"] == "staged" and dtype != "c128":
+        opts.update(lds_qubits=0, lds_regs=0)
+    p = q.Plan(circ, "c128", **opts)
+    p.execute_from_zero(s)
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
-    done = 0
-    for kw, args in c.ops:
-        oracle.apply_op(a, c.n, kw, args)
-        done += 1
-        if time.perf_counter() - t0 > budget_s and done >= 8:
-            break
-    dt = time.perf_counter() - t0
-    rate = done / dt
-    scaled = rate * 2.0 ** (n_sample - n_full)
-    threads = oracle.threads()
-    return {"value": scaled, "unit": "gates/s", "cores": threads, "kind": "oracle",
-            "sample": f"first {done} gates of the {n_sample}-qubit complex128 brickwork circuit (seed {seed}) in "
-                      f"{dt:.1f} s = {rate:.2f} gates/s at {n_sample} qubits, scaled by 2^({n_sample}-{n_full}) "
-                      f"to {n_full} qubits (work per gate is O(2^n))"}
+    reps = 5
+    for _ in range(reps):
+        p.execute_from_zero(s)
+    torch.cuda.synchronize()
+    gsecs = (time.perf_counter() - t0) / reps
+    d = float(np.max(np.abs(s.download() - psi)))
+    gpu = {"method": opts["method"], "seconds": round(gsecs, 5), "gates_per_s": round(full["gates"] / gsecs, 1),
+           "max_abs_diff_vs_oracle": d}
+    p.close()
+    s.close()
+    del s, psi
+    # one thread, in a child process (OpenMP reads its thread count at start-up)
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    code = ("import json, sys; sys.path.insert(0, %r); import bench; r, _ = bench._oracle_run_json(%d, %d, %d); "
+            "print(json.dumps(r))" % (ROOT, args.cpu_n1, layers, seed))
+    r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, check=True)
+    one = json.loads(r.stdout.strip().splitlines()[-1])
+    c1 = q.parse_circuit(wl.brickwork_circuit(args.cpu_n1, layers, seed))
+    p1 = q.Plan(c1, "c128", method="plain")
+    bytes1 = p1.info["alg_bytes"]
+    p1.close()
+    rate = full["gates"] / full["seconds"]
+    return {"value": round(rate, 3), "unit": "gates/s", "cores": full["threads"], "kind": "oracle",
+            "sample": f"the whole {n}-qubit complex128 brickwork circuit of the same family (20 layers, seed {seed}, "
+                      f"{full['gates']} gates) from |0...0>, measured: {full['seconds']:.2f} s on {full['threads']} "
+                      f"threads; no scaling to other sizes",
+            "n_qubits": n, "seconds": round(full["seconds"], 3), "GBps": round(alg_bytes / full["seconds"] / 1e9, 2),
+            "gpu_same_circuit": gpu, "gpu_speedup_same_circuit": round(full["seconds"] / gsecs, 1),
+            "one_thread": {"n_qubits": args.cpu_n1, "gates": one["gates"], "seconds": round(one["seconds"], 3),
+                           "gates_per_s": round(one["gates"] / one["seconds"], 3),
+                           "GBps": round(bytes1 / one["seconds"] / 1e9, 3), "threads": one["threads"]}}
 
 
 def sweep_mode(args) -> int:
@@ -311,8 +362,9 @@ def main() -> int:
     ap.add_argument("--lds", type=int, default=0, help="resident qubits per LDS block (staged plans)")
     ap.add_argument("--lds-regs", type=int, default=0, help="log2 amplitudes per thread (staged plans)")
     ap.add_argument("--plain-runs", type=int, default=1, help="timed runs of the plain per-gate plan (0 = skip)")
-    ap.add_argument("--cpu-budget", type=float, default=15.0)
-    ap.add_argument("--cpu-n", type=int, default=27)
+    ap.add_argument("--fused-runs", type=int, default=1, help="timed runs of the fused k = 5 plan (0 = skip)")
+    ap.add_argument("--cpu-n", type=int, default=28, help="qubits of the oracle run on all host threads")
+    ap.add_argument("--cpu-n1", type=int, default=20, help="qubits of the one-thread oracle run")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--renorm-every", type=int, default=None,
                     help="layers between FP64 renormalisations (default 10 for complex64, 0 = none for complex128)")
@@ -374,15 +426,18 @@ def main() -> int:
     log(f"plan {popts}: {info}")
     norms = []
 
-    def step(timed: bool):
-        state.set_basis(0)
+    def run(pl, timed: bool):
+        """One run of the circuit from |0...0>: the first plan generates the initial state (a staged
+        plan inside its first pass), then the groups in order, with FP64 renormalisation after each."""
         ms, kd, fk = [], [], []
-        for p in plans:
+        for i, p in enumerate(pl):
             if timed:
-                a, b, c = p.execute_timed(state)
+                a, b, c = p.execute_timed(state, from_zero=(i == 0))
                 ms.append(a)
                 kd.append(b)
                 fk.append(c)
+            elif i == 0:
+                p.execute_from_zero(state)
             else:
                 p.execute(state)
             if renorm:
@@ -390,7 +445,7 @@ def main() -> int:
         return (np.concatenate(ms), np.concatenate(kd), np.concatenate(fk)) if timed else None
 
     for i in range(args.warmup):
-        step(False)
+        run(plans, False)
         torch.cuda.synchronize()
         log(f"warmup {i + 1}/{args.warmup} done")
     norms.clear()
@@ -398,59 +453,15 @@ def main() -> int:
     t0 = time.perf_counter()
     launch_ms, kinds, fks = [], None, None
     for i in range(args.steps):
-        ms, kinds, fks = step(True)
+        ms, kinds, fks = run(plans, True)
         launch_ms.append(ms)
         log(f"step {i + 1}/{args.steps}: {ms.sum():.1f} ms in {len(ms)} launches")
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms_per_step = 1000.0 * wall / args.steps
     gates_per_s = G / (wall / args.steps)
-    plan_bytes = info["alg_bytes"]
-    eff_gbps = plan_bytes / (wall / args.steps) / 1e9
-
-    # dominant kernel of the timed plan: the class (and fused width) with the most total time
-    L = np.stack(launch_ms)  # steps x launches
-    avg_per_launch = L.mean(axis=0)
-    classes = {}
-    for i, (kd, fk) in enumerate(zip(kinds, fks)):
-        key = (int(kd), int(fk))
-        classes.setdefault(key, []).append(i)
-    dom_key = max(classes, key=lambda k: avg_per_launch[classes[k]].sum())
-    dom_idx = classes[dom_key]
-    dom_avg_ms = float(avg_per_launch[dom_idx].mean())
-    dom_name = KERNEL_NAMES[dom_key[0]] + (f"_k{dom_key[1]}" if dom_key[1] else "")
-    if KERNEL_NAMES[dom_key[0]] == "staged":
-        dom_name += f"_m{info['lds_qubits']}r{info['lds_regs']}"
-    full_sweep_bytes = 2.0 * amp * 2 ** n
-    kname = KERNEL_NAMES[dom_key[0]]
-    dom_bytes = full_sweep_bytes  # fused blocks, staged passes and general sweeps read and write every amplitude
-    if kname in ("fused_mfma", "fused_valu"):
-        dom_flops = 8.0 * 2 ** (n + dom_key[1])
-        mfma = kname == "fused_mfma"
-        alu_peak = (FP64_PEAK_TFLOPS if dtype == "c128" else FP32_MFMA_PEAK_TFLOPS) if mfma else VALU_PEAK_TFLOPS
-    elif kname == "staged":
-        dom_flops = info["alg_flops"] / max(1, info["passes"])  # per pass, averaged over the passes
-        mfma, alu_peak = False, VALU_PEAK_TFLOPS
-    else:
-        dom_flops, mfma, alu_peak = 0.0, False, VALU_PEAK_TFLOPS
-    secs = dom_avg_ms / 1e3
-    hbm_gbps = dom_bytes / secs / 1e9
-    alu_tf = dom_flops / secs / 1e12
-    t_hbm = dom_bytes / (HBM_PEAK_GBPS * 1e9)
-    t_alu = dom_flops / (alu_peak * 1e12)
-    traffic = load_traffic(workload, dom_name)
-    if t_alu > t_hbm:
-        roof = {"bound": "mfma" if mfma else "alu", "achieved": round(alu_tf, 2), "peak": alu_peak, "unit": "TFLOP/s",
-                "frac": round(alu_tf / alu_peak, 4), "traffic": traffic}
-    else:
-        roof = {"bound": "hbm", "achieved": round(hbm_gbps, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                "frac": round(hbm_gbps / HBM_PEAK_GBPS, 4), "traffic": traffic}
-    roof.update({"kernel": dom_name, "launches": len(dom_idx), "avg_launch_ms": round(dom_avg_ms, 3),
-                 "alg_bytes_per_launch": dom_bytes, "alg_flops_per_launch": dom_flops,
-                 "hbm_GBps": round(hbm_gbps, 1), "hbm_frac": round(hbm_gbps / HBM_PEAK_GBPS, 4)})
-    if dom_flops:
-        roof.update({"alu_TFLOPs": round(alu_tf, 2), "alu_peak": alu_peak, "alu_frac": round(alu_tf / alu_peak, 4),
-                     "floor_ms": {"hbm": round(t_hbm * 1e3, 2), "alu": round(t_alu * 1e3, 2)}})
+    eff_gbps = info["alg_bytes"] / (wall / args.steps) / 1e9
+    roof = roofline(np.stack(launch_ms), kinds, fks, info, n, dtype, workload)
 
     out = {
         "metric": METRIC, "value": round(gates_per_s, 3), "unit": "gates/s", "n_gpus": 1,
@@ -476,44 +487,113 @@ def main() -> int:
         out["norm_before_renormalisation"] = last
         out["max_norm_drift"] = max(abs(x - 1.0) for x in last)
 
-    # the plain per-gate plan, timed beside it
-    if args.plain_runs > 0:
-        pplans = [q.Plan(c, dtype, method="plain") for c in circs]
-        pbytes = sum(p.info["alg_bytes"] for p in pplans)
-        pms = []
-        pk = None
-        for r in range(args.plain_runs):
-            state.set_basis(0)
+    # the plain per-gate plan (one sweep per gate) and the fused k = 5 plan (dense 32 x 32 blocks on
+    # the matrix cores), each timed whole beside the headline plan
+    full_sweep_bytes = 2.0 * amp * 2 ** n
+    for leg, legopts, runs in (("plain", dict(method="plain"), args.plain_runs),
+                               ("fused", dict(method="fused", fuse_k=5), args.fused_runs)):
+        if runs <= 0 or (leg == popts["method"] and leg != "fused"):
+            continue
+        lplans = [q.Plan(c, dtype, **legopts) for c in circs]
+        lbytes = sum(p.info["alg_bytes"] for p in lplans)
+        walls, lms, lk, lf = [], [], None, None
+        for r in range(runs):
             torch.cuda.synchronize()
             t1 = time.perf_counter()
-            parts = []
-            for p in pplans:
-                parts.append(p.execute_timed(state))
-                if renorm:
-                    state.renormalize()
+            ms, lk, lf = run(lplans, True)
             torch.cuda.synchronize()
-            ms = np.concatenate([m for m, _, _ in parts])
-            pk = np.concatenate([k for _, k, _ in parts])
-            pms.append((time.perf_counter() - t1, ms))
-            log(f"plain run {r + 1}/{args.plain_runs}: {pms[-1][0]:.2f} s")
-        pwall = float(np.mean([w for w, _ in pms]))
-        pl = np.mean(np.stack([m for _, m in pms]), axis=0)
-        gen = [i for i, kd in enumerate(pk) if kd == 0]
-        gen_ms = float(pl[gen].mean()) if gen else None
-        out["plain"] = {
-            "gates_per_s": round(G / pwall, 3), "s_per_run": round(pwall, 3),
-            "eff_GBps": round(pbytes / pwall / 1e9, 1),
-            "hbm_frac": round(pbytes / pwall / 1e9 / HBM_PEAK_GBPS, 4),
-            "general_sweep_avg_ms": round(gen_ms, 3) if gen_ms else None,
-            "general_sweep_GBps": round(full_sweep_bytes / (gen_ms / 1e3) / 1e9, 1) if gen_ms else None,
-        }
-        out["speedup_vs_plain"] = round(gates_per_s / (G / pwall), 2)
+            walls.append(time.perf_counter() - t1)
+            lms.append(ms)
+            log(f"{leg} run {r + 1}/{runs}: {walls[-1]:.2f} s in {len(ms)} launches")
+        lwall = float(np.mean(walls))
+        linfo = dict(lplans[0].info)
+        for k in ("gates", "launches", "passes", "alg_bytes", "alg_flops"):
+            linfo[k] = sum(p.info[k] for p in lplans)
+        entry = {"gates_per_s": round(G / lwall, 3), "s_per_run": round(lwall, 3), "launches": int(linfo["launches"]),
+                 "eff_GBps": round(lbytes / lwall / 1e9, 1), "hbm_frac": round(lbytes / lwall / 1e9 / HBM_PEAK_GBPS, 4),
+                 "roofline": roofline(np.stack(lms), lk, lf, linfo, n, dtype, workload)}
+        if leg == "plain":
+            L = np.mean(np.stack(lms), axis=0)
+            gen = [i for i, kd in enumerate(lk) if kd == 0]
+            gen_ms = float(L[gen].mean()) if gen else None
+            entry["general_sweep_avg_ms"] = round(gen_ms, 3) if gen_ms else None
+            entry["general_sweep_GBps"] = round(full_sweep_bytes / (gen_ms / 1e3) / 1e9, 1) if gen_ms else None
+        out[leg] = entry
+        out[f"speedup_vs_{leg}"] = round(gates_per_s / (G / lwall), 2)
+        for p in lplans:
+            p.close()
 
     if not args.no_cpu:
         log("cpu baseline (oracle) ...")
-        out["cpu_baseline"] = cpu_baseline(n, args.layers, args.seed, args.cpu_budget, min(args.cpu_n, n))
+        out["cpu_baseline"] = cpu_baseline(args, popts, dtype)
     print(json.dumps(out), flush=True)
     return 0
+
+
+def roofline(L, kinds, fks, info, n, dtype, workload) -> dict:
+    """The dominant kernel of a plan (the class, and fused width, with the most total time over the
+    timed runs) against the bound that limits it. L: runs x launches of HIP-event durations (ms).
+    Algorithmic work per launch: a staged pass or fused block reads and writes all 2^n amplitudes
+    once; a fused k-qubit block does 8 * 2^(n+k) flops on the matrix cores; a staged pass does the
+    plan's 2x2 flops (14 per amplitude per dense 2x2) divided over its passes."""
+    import numpy as np
+
+    from paper_quant_ph_0608239_amd._lib import KERNEL_NAMES
+    amp = 16 if dtype == "c128" else 8
+    avg = L.mean(axis=0)
+    classes = {}
+    for i, (kd, fk) in enumerate(zip(kinds, fks)):
+        classes.setdefault((int(kd), int(fk)), []).append(i)
+    key = max(classes, key=lambda k: avg[classes[k]].sum())
+    idx = classes[key]
+    dom_ms = float(avg[idx].mean())
+    kname = KERNEL_NAMES[key[0]]
+    name = kname + (f"_k{key[1]}" if key[1] else "")
+    if kname == "staged":
+        name += f"_m{info['lds_qubits']}r{info['lds_regs']}"
+    dom_bytes = 2.0 * amp * 2 ** n
+    issued = None
+    if kname in ("fused_mfma", "fused_valu"):
+        flops = 8.0 * 2 ** (n + key[1])
+        mfma = kname == "fused_mfma"
+        peak = (FP64_PEAK_TFLOPS if dtype == "c128" else FP32_MFMA_PEAK_TFLOPS) if mfma else \
+            (FP64_VALU_PEAK_TFLOPS if dtype == "c128" else FP32_VALU_PEAK_TFLOPS)
+    elif kname == "staged":
+        flops = info["alg_flops"] / max(1, info["passes"])
+        mfma = False
+        peak = FP64_VALU_PEAK_TFLOPS if dtype == "c128" else FP32_VALU_PEAK_TFLOPS
+        # a dense 2x2 with a real first column issues 12 FMAs (24 flops) per pair, against the 28 of the
+        # algorithmic count; complex64 code has no packed FP32 instructions, so it can issue at most
+        # half the published FP32 vector rate
+        issued = {"flops_per_launch": flops * 24.0 / 28.0, "frac_of_peak": None,
+                  "peak_as_compiled": FP64_VALU_PEAK_TFLOPS if dtype == "c128" else FP32_UNPACKED_PEAK_TFLOPS}
+    else:
+        flops, mfma, peak = 0.0, False, FP64_VALU_PEAK_TFLOPS
+    secs = dom_ms / 1e3
+    gbps = dom_bytes / secs / 1e9
+    tf = flops / secs / 1e12
+    t_hbm = dom_bytes / (HBM_PEAK_GBPS * 1e9)
+    t_alu = flops / (peak * 1e12)
+    traffic = load_traffic(workload, name)
+    if t_alu > t_hbm:
+        roof = {"bound": "mfma" if mfma else "alu", "achieved": round(tf, 2), "peak": peak, "unit": "TFLOP/s",
+                "frac": round(tf / peak, 4), "traffic": traffic}
+    else:
+        roof = {"bound": "hbm", "achieved": round(gbps, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                "frac": round(gbps / HBM_PEAK_GBPS, 4), "traffic": traffic}
+    roof.update({"kernel": name, "launches": len(idx), "avg_launch_ms": round(dom_ms, 3),
+                 "alg_bytes_per_launch": dom_bytes, "alg_flops_per_launch": flops,
+                 "hbm_GBps": round(gbps, 1), "hbm_frac": round(gbps / HBM_PEAK_GBPS, 4)})
+    if flops:
+        roof.update({"alu_TFLOPs": round(tf, 2), "alu_peak": peak, "alu_frac": round(tf / peak, 4),
+                     "floor_ms": {"hbm": round(t_hbm * 1e3, 2), "alu": round(t_alu * 1e3, 2)}})
+    if issued:
+        itf = issued["flops_per_launch"] / secs / 1e12
+        issued["TFLOPs"] = round(itf, 2)
+        issued["frac_of_peak"] = round(itf / peak, 4)
+        issued["frac_as_compiled"] = round(itf / issued["peak_as_compiled"], 4)
+        roof["issued"] = issued
+    return roof
 
 
 if __name__ == "__main__":

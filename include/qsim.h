@@ -127,11 +127,12 @@ int qsim_apply_fused(qsim_state *s, int k, const int *qubits, const double *U);
  * with x = the value of qubits x_first .. x_first+x_qubits-1 and z = the value of qubits
  * f_first .. f_first+f_qubits-1 of a basis state, |x>|z> -> |x>|z XOR (y^x mod G)>. On a state whose
  * f-register is |0> this writes f(x) = y^x mod G into it. The map is a permutation of basis states
- * (its own inverse); amplitudes are moved without arithmetic, so the result is bit-exact. A table of
- * the 2^x_qubits powers (4 bytes each) is allocated on the device for the call; the call returns
- * after the permutation has finished on the state's stream.
+ * (its own inverse); amplitudes are moved without arithmetic, so the result is bit-exact. The powers
+ * come from two tables of at most 2^15 residues each, built on the device in the state's scratch
+ * buffer (y^xl and y^(xh 2^h) for the low and high halves of x); nothing is allocated and the call is
+ * asynchronous on the state's stream like the other gates.
  * EINVAL: registers overlap or leave the state, x_qubits outside 1..30, f_qubits outside 1..32,
- * G < 2, G > 2^f_qubits or G >= 2^32. ENOMEM / EDEVICE from the table allocation or the launch. */
+ * G < 2, G > 2^f_qubits or G >= 2^32. EDEVICE from the launch. */
 int qsim_apply_modexp(qsim_state *s, int x_first, int x_qubits, int f_first, int f_qubits, uint64_t y, uint64_t G);
 
 /* ---------------------------------------------------------------------------------------------
@@ -182,13 +183,18 @@ typedef enum {
     QSIM_OP_RZ,         /* diag(e^{-i theta/2}, e^{+i theta/2}) */
     QSIM_OP_V,          /* V(theta) of Eq. COMM4 (controlled: Eq. NUM7) */
     QSIM_OP_SWAP,       /* quantum swap of target and target2 */
+    QSIM_OP_RK,         /* R(2 pi / 2^k) = diag(1, e^{2 pi i / 2^k}) with k = target2 (0..63), the phase shift
+                           of the Fourier transform and the register adders (Fig. gates, Sec. V); the
+                           angle is formed from k in FP64 by the library (on the device for plain and
+                           staged plans and batches, on the host where gates are fused into matrices) */
+    QSIM_OP_RKDG,       /* R(-2 pi / 2^k), the inverse of QSIM_OP_RK */
     QSIM_OP_COUNT_
 } qsim_op;
 
 typedef struct qsim_gate {
     int32_t op;        /* qsim_op */
     int32_t target;    /* target qubit (QSIM_OP_SWAP: first qubit) */
-    int32_t target2;   /* QSIM_OP_SWAP: second qubit; ignored otherwise */
+    int32_t target2;   /* QSIM_OP_SWAP: second qubit; QSIM_OP_RK / QSIM_OP_RKDG: k; ignored otherwise */
     int32_t reserved;  /* must be 0 */
     uint64_t controls; /* control mask */
     double theta;      /* angle of QSIM_OP_PHASE, QSIM_OP_RZ, QSIM_OP_V */
@@ -234,6 +240,11 @@ int qsim_plan_create(int n, int dtype, const qsim_gate *gates, int64_t ngates, c
 int qsim_plan_get_info(const qsim_plan *p, qsim_plan_info *info);
 /* Apply the plan to the state (asynchronous on its stream). EINVAL if n or dtype differ. */
 int qsim_plan_execute(qsim_plan *p, qsim_state *s);
+/* Run the plan's circuit from |0...0> (the state's previous contents are ignored): the same result as
+ * qsim_set_basis(s, 0) followed by qsim_plan_execute, but a staged plan generates the initial state
+ * inside its first pass (no separate write of the state and no read of it). Never through a graph.
+ * Asynchronous on the state's stream. EINVAL as qsim_plan_execute. */
+int qsim_plan_execute_from_zero(qsim_plan *p, qsim_state *s);
 int qsim_plan_free(qsim_plan *p);
 
 /* Autotuner: lower the circuit with every candidate method and parameter set (plain if
@@ -261,11 +272,25 @@ enum {
     QSIM_KERNEL_STAGED = 6      /* LDS-resident multi-gate pass */
 };
 
-/* Execute like qsim_plan_execute (never through a graph) with a pair of HIP events recorded on the
- * state's stream around every launch, then synchronise. launch_ms[i] receives the duration of
- * launch i and kind[i] its QSIM_KERNEL_* class, fused_k[i] the fused width (0 if none); each array
- * needs info.launches entries and may be NULL. */
-int qsim_plan_execute_timed(qsim_plan *p, qsim_state *s, double *launch_ms, int32_t *kind, int32_t *fused_k);
+/* Kernel forms of an LDS-staged pass, reported by qsim_plan_launches. */
+enum {
+    QSIM_STAGED_FULL = 0, /* block in an LDS buffer of its full size */
+    QSIM_STAGED_HALF = 1, /* every LDS round trip in two halves through a buffer of half the block */
+    QSIM_STAGED_WAVE = 2  /* half buffer, every half a set of whole wavefronts */
+};
+
+/* The launches of a plan without running it (host only): kind[i] receives the QSIM_KERNEL_* class of
+ * launch i and variant[i] its form: the fused width for fused gates, the QSIM_STAGED_* form for
+ * staged passes, 0 otherwise. Each array needs info.launches entries and may be NULL. */
+int qsim_plan_launches(const qsim_plan *p, int32_t *kind, int32_t *variant);
+
+/* Execute like qsim_plan_execute (never through a graph), or like qsim_plan_execute_from_zero if
+ * from_zero is nonzero, with a pair of HIP events recorded on the state's stream around every launch,
+ * then synchronise. launch_ms[i] receives the duration of launch i and kind[i] its QSIM_KERNEL_* class,
+ * fused_k[i] the fused width (0 if none); each array needs info.launches entries and may be NULL (a
+ * plain or fused plan run from zero writes |0...0> first, outside the timed launches). */
+int qsim_plan_execute_timed(qsim_plan *p, qsim_state *s, int from_zero, double *launch_ms, int32_t *kind,
+                            int32_t *fused_k);
 
 /* ---------------------------------------------------------------------------------------------
  * Batches of independent small circuits in one persistent launch

@@ -14,12 +14,16 @@ import math
 import numpy as np
 
 from . import _lib
-from ._lib import (PLAN_AUTO, PLAN_FUSED, PLAN_PLAIN, PLAN_STAGED, QSIM_C64, QSIM_C128, Gate, QsimError,
-                   check, lib)
+from ._lib import (PLAN_AUTO, PLAN_FUSED, PLAN_PLAIN, PLAN_STAGED, QSIM_C64, QSIM_C128, STAGED_FULL, STAGED_HALF,
+                   STAGED_WAVE, Gate, QsimError, check, lib)
 from .circuit import Circuit, parse_circuit
 
 __all__ = ["State", "Plan", "Batch", "Circuit", "parse_circuit", "QsimError", "lib", "dtype_code",
-           "PLAN_PLAIN", "PLAN_FUSED", "PLAN_STAGED", "PLAN_AUTO", "QSIM_C64", "QSIM_C128"]
+           "PLAN_PLAIN", "PLAN_FUSED", "PLAN_STAGED", "PLAN_AUTO", "QSIM_C64", "QSIM_C128",
+           "STAGED_FULL", "STAGED_HALF", "STAGED_WAVE", "KERNEL_STAGED", "KERNEL_FUSED_MFMA"]
+
+KERNEL_STAGED = 6
+KERNEL_FUSED_MFMA = 5
 
 
 def dtype_code(dtype) -> int:
@@ -124,7 +128,7 @@ class State:
                                      flat.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
 
     def apply_modexp(self, x_first: int, x_qubits: int, f_first: int, f_qubits: int, y: int, G: int):
-        """|x>|z> -> |x>|z XOR (y^x mod G)> (Shor's conditional operation; returns when done)."""
+        """|x>|z> -> |x>|z XOR (y^x mod G)> (Shor's conditional operation; asynchronous)."""
         check(lib().qsim_apply_modexp(self.handle, int(x_first), int(x_qubits), int(f_first), int(f_qubits),
                                       int(y), int(G)))
 
@@ -201,14 +205,29 @@ class Plan:
     def execute(self, state: State):
         check(lib().qsim_plan_execute(self.handle, state.handle))
 
-    def execute_timed(self, state: State):
-        """Execute with HIP events around every launch (synchronises). Returns (ms, kind, fused_k)
-        numpy arrays, one entry per launch."""
+    def execute_from_zero(self, state: State):
+        """Run the circuit from |0...0> (the state's contents are ignored; a staged plan generates the
+        initial state in its first pass)."""
+        check(lib().qsim_plan_execute_from_zero(self.handle, state.handle))
+
+    def launches(self):
+        """(kind, variant) numpy arrays, one entry per launch, without running the plan: the kernel
+        class of each launch, and its fused width or staged form (STAGED_FULL / HALF / WAVE)."""
+        L = int(self.info["launches"])
+        kind = np.zeros(max(L, 1), dtype=np.int32)
+        var = np.zeros(max(L, 1), dtype=np.int32)
+        check(lib().qsim_plan_launches(self.handle, kind.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                       var.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))))
+        return kind[:L], var[:L]
+
+    def execute_timed(self, state: State, from_zero: bool = False):
+        """Execute (from |0...0> if from_zero) with HIP events around every launch (synchronises).
+        Returns (ms, kind, fused_k) numpy arrays, one entry per launch."""
         L = int(self.info["launches"])
         ms = np.zeros(max(L, 1), dtype=np.float64)
         kind = np.zeros(max(L, 1), dtype=np.int32)
         fk = np.zeros(max(L, 1), dtype=np.int32)
-        check(lib().qsim_plan_execute_timed(self.handle, state.handle,
+        check(lib().qsim_plan_execute_timed(self.handle, state.handle, int(bool(from_zero)),
                                             ms.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                                             kind.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
                                             fk.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))))

@@ -20,9 +20,11 @@ _ERRNAMES = {EINVAL: "EINVAL", ENOMEM: "ENOMEM", EDEVICE: "EDEVICE", EUNSUPPORTE
 OPS = {
     "MATRIX": 0, "H": 1, "X": 2, "Y": 3, "Z": 4, "S": 5, "SDG": 6, "T": 7, "TDG": 8,
     "RX90": 9, "RX90DG": 10, "RY90": 11, "RY90DG": 12, "PHASE": 13, "RZ": 14, "V": 15, "SWAP": 16,
+    "RK": 17, "RKDG": 18,
 }
 
 PLAN_PLAIN, PLAN_FUSED, PLAN_STAGED, PLAN_AUTO = 0, 1, 2, 3
+STAGED_FULL, STAGED_HALF, STAGED_WAVE = 0, 1, 2
 KERNEL_NAMES = {0: "general", 1: "phase", 2: "diag", 3: "swap", 4: "fused_valu", 5: "fused_mfma", 6: "staged"}
 
 
@@ -92,7 +94,10 @@ SIGNATURES = {
     "qsim_plan_get_info": (_i32, [_vp, ctypes.POINTER(PlanInfo)]),
     "qsim_plan_execute": (_i32, [_vp, _vp]),
     "qsim_plan_free": (_i32, [_vp]),
-    "qsim_plan_execute_timed": (_i32, [_vp, _vp, _dp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]),
+    "qsim_plan_launches": (_i32, [_vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]),
+    "qsim_plan_execute_from_zero": (_i32, [_vp, _vp]),
+    "qsim_plan_execute_timed": (_i32, [_vp, _vp, _i32, _dp, ctypes.POINTER(ctypes.c_int32),
+                                       ctypes.POINTER(ctypes.c_int32)]),
     "qsim_plan_tune": (_i32, [_i32, _i32, ctypes.POINTER(Gate), _i64, _vp, _i32, _i32, ctypes.POINTER(PlanOpts), _dp,
                               ctypes.POINTER(PlanOpts), _dp, _i32, ctypes.POINTER(_i32)]),
     "qsim_batch_create": (_i32, [_i32, ctypes.POINTER(_i32), ctypes.POINTER(_i64), ctypes.POINTER(Gate), _i32,

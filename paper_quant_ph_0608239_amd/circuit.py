@@ -3,11 +3,10 @@
 The text format is one gate per line, a keyword followed by values, with `!`/`#` comments, in the
 style of the paper's App. A input file: QUBITS n, INITIAL STATE x, then gate lines such as
 `H 0`, `CNOT 0 1`, `CRK 2 5 3`, `U 4 <8 hex floats>`. Floats may be decimal or C99 hex.
-Controlled gates list the control(s) first and the target last.
+Controlled gates list the control(s) first and the target last. `RK t k` / `CRK c t k` carry the
+integer k of the phase shift 2 pi / 2^k; the library forms the angle.
 """
 from __future__ import annotations
-
-import math
 
 from ._lib import OPS, Gate
 
@@ -33,11 +32,6 @@ def _gate(op: str, target: int, controls: int = 0, theta: float = 0.0, target2: 
         for i, v in enumerate(u):
             g.u[i] = v
     return g
-
-
-def rk_theta(k: int, sign: float = 1.0) -> float:
-    """The phase-shift angle 2 pi / 2^k of the paper's Fig. gates, as an exact FP64 scaling of 2 pi."""
-    return sign * math.ldexp(2.0 * math.pi, -int(k))
 
 
 class Circuit:
@@ -77,7 +71,7 @@ def parse_circuit(text: str) -> Circuit:
         elif kw == "R":
             g = _gate("PHASE", int(a[0]), theta=_f(a[1]))
         elif kw in ("RK", "RKDG"):
-            g = _gate("PHASE", int(a[0]), theta=rk_theta(int(a[1]), -1.0 if kw == "RKDG" else 1.0))
+            g = _gate(kw, int(a[0]), target2=int(a[1]))
         elif kw == "RZ":
             g = _gate("RZ", int(a[0]), theta=_f(a[1]))
         elif kw == "U":
@@ -89,8 +83,7 @@ def parse_circuit(text: str) -> Circuit:
         elif kw == "CPHASE":
             g = _gate("PHASE", int(a[1]), controls=1 << int(a[0]), theta=_f(a[2]))
         elif kw in ("CRK", "CRKDG"):
-            g = _gate("PHASE", int(a[1]), controls=1 << int(a[0]),
-                      theta=rk_theta(int(a[2]), -1.0 if kw == "CRKDG" else 1.0))
+            g = _gate(kw[1:], int(a[1]), controls=1 << int(a[0]), target2=int(a[2]))
         elif kw == "CV":
             g = _gate("V", int(a[1]), controls=1 << int(a[0]), theta=_f(a[2]))
         elif kw == "TOFFOLI":

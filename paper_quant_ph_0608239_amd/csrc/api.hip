@@ -73,7 +73,15 @@ static int apply_matrix(qsim_state *s, uint64_t cmask, int target, const double 
     }
 }
 
-// FP64 matrices of the named gates (host); angle gates that run as phase kernels never come here
+double phase_angle(const qsim_gate &g)
+{
+    if (g.op == QSIM_OP_RK) return std::ldexp(kTwoPi, -g.target2);
+    if (g.op == QSIM_OP_RKDG) return -std::ldexp(kTwoPi, -g.target2);
+    return g.theta;
+}
+
+// FP64 matrices of the named gates (host); the per-gate path and the staged passes evaluate angle
+// gates on the device instead
 int gate_matrix(const qsim_gate &g, double u[8])
 {
     const double h = 1.0 / std::sqrt(2.0);
@@ -94,7 +102,13 @@ int gate_matrix(const qsim_gate &g, double u[8])
     case QSIM_OP_RX90DG: setm(h, 0, 0, -h, 0, -h, h, 0); break;   // conjugate transpose
     case QSIM_OP_RY90: setm(h, 0, h, 0, -h, 0, h, 0); break;      // (1/sqrt2)[[1, 1], [-1, 1]]
     case QSIM_OP_RY90DG: setm(h, 0, -h, 0, h, 0, h, 0); break;    // transpose
-    case QSIM_OP_PHASE: setm(1, 0, 0, 0, 0, 0, std::cos(g.theta), std::sin(g.theta)); break;
+    case QSIM_OP_PHASE:
+    case QSIM_OP_RK:
+    case QSIM_OP_RKDG: {
+        const double th = phase_angle(g);
+        setm(1, 0, 0, 0, 0, 0, std::cos(th), std::sin(th));
+        break;
+    }
     case QSIM_OP_RZ:
         setm(std::cos(0.5 * g.theta), -std::sin(0.5 * g.theta), 0, 0, 0, 0, std::cos(0.5 * g.theta), std::sin(0.5 * g.theta));
         break;
@@ -122,6 +136,8 @@ int validate_gate(const qsim_gate &g, int n)
     }
     if ((g.op == QSIM_OP_PHASE || g.op == QSIM_OP_RZ || g.op == QSIM_OP_V) && !std::isfinite(g.theta))
         return set_error(QSIM_EINVAL, "gate: angle is not finite");
+    if ((g.op == QSIM_OP_RK || g.op == QSIM_OP_RKDG) && (g.target2 < 0 || g.target2 > 63))
+        return set_error(QSIM_EINVAL, "gate: RK needs 0 <= k <= 63 in target2");
     return QSIM_OK;
 }
 
@@ -136,6 +152,10 @@ int apply_gate_record(qsim_state *s, const qsim_gate &g)
     if (g.op == QSIM_OP_PHASE) {
         const double c[2] = {g.theta, 0.0};
         return launch_phase(s, make_index_map(g.controls | tbit, g.controls | tbit), c, DiagMode::Angles);
+    }
+    if (g.op == QSIM_OP_RK || g.op == QSIM_OP_RKDG) {
+        const double c[2] = {g.op == QSIM_OP_RK ? 1.0 : -1.0, double(g.target2)};
+        return launch_phase(s, make_index_map(g.controls | tbit, g.controls | tbit), c, DiagMode::Pow2);
     }
     if (g.op == QSIM_OP_RZ) {
         const double d[4] = {-0.5 * g.theta, 0.0, 0.5 * g.theta, 0.0};

@@ -28,9 +28,10 @@ int launch_fused_valu(qsim_state *s, int k, const int *qubits, const double *U);
 struct StagedPlan;  // staged.hip
 int staged_build(int n, int dtype, const std::vector<qsim_gate> &gates, int lds_qubits, int lds_regs, StagedPlan **out,
                  qsim_plan_info *info);
-int staged_execute(StagedPlan *p, qsim_state *s);
-int staged_execute_timed(StagedPlan *p, qsim_state *s, double *ms, int32_t *kind, int32_t *fk);
+int staged_execute(StagedPlan *p, qsim_state *s, bool from_zero);
+int staged_execute_timed(StagedPlan *p, qsim_state *s, bool from_zero, double *ms, int32_t *kind, int32_t *fk);
 void staged_free(StagedPlan *p);
+void staged_launch_variants(const StagedPlan *p, int32_t *variant);
 
 }  // namespace qsim
 
@@ -63,7 +64,7 @@ double touched(const qsim_gate &g, int n)
     const int nc = __builtin_popcountll(g.controls);
     const double full = std::ldexp(1.0, n - nc);
     if (g.op == QSIM_OP_SWAP) return full / 2;
-    if (g.op == QSIM_OP_PHASE) return full / 2;
+    if (phase_op(g.op)) return full / 2;
     double u[8];
     if (gate_matrix(g, u)) return full;
     if (classify(u) == Kind::Phase1) return full / 2;
@@ -77,7 +78,7 @@ double valu_flops(const qsim_gate &g, int n)
 {
     const double t = touched(g, n);
     if (g.op == QSIM_OP_SWAP) return 0.0;
-    if (g.op == QSIM_OP_PHASE || g.op == QSIM_OP_RZ) return 6.0 * t;
+    if (phase_op(g.op) || g.op == QSIM_OP_RZ) return 6.0 * t;
     double u[8];
     if (gate_matrix(g, u)) return 6.0 * t;
     switch (classify(u)) {
@@ -261,7 +262,7 @@ static int kernel_kind(const Step &st)
     if (st.type == 1) return st.k >= 4 ? QSIM_KERNEL_FUSED_MFMA : QSIM_KERNEL_FUSED_VALU;
     const qsim_gate &g = st.g;
     if (g.op == QSIM_OP_SWAP) return QSIM_KERNEL_SWAP;
-    if (g.op == QSIM_OP_PHASE) return QSIM_KERNEL_PHASE;
+    if (phase_op(g.op)) return QSIM_KERNEL_PHASE;
     if (g.op == QSIM_OP_RZ) return QSIM_KERNEL_DIAG;
     double u[8];
     if (gate_matrix(g, u)) return QSIM_KERNEL_GENERAL;
@@ -280,9 +281,11 @@ static int run_step(qsim_plan *p, qsim_state *s, const Step &st)
     return launch_fused_valu(s, st.k, st.qubits, st.U.data());
 }
 
-static int run_steps_timed(qsim_plan *p, qsim_state *s, double *ms, int32_t *kind, int32_t *fk)
+static int run_steps_timed(qsim_plan *p, qsim_state *s, bool from_zero, double *ms, int32_t *kind, int32_t *fk)
 {
-    if (p->staged) return staged_execute_timed(p->staged, s, ms, kind, fk);
+    if (p->staged) return staged_execute_timed(p->staged, s, from_zero, ms, kind, fk);
+    if (from_zero)
+        if (int rc = launch_set_basis(s, 0)) return rc;
     const size_t L = p->steps.size();
     std::vector<hipEvent_t> ev(2 * L, nullptr);
     for (auto &e : ev) QSIM_HIP(hipEventCreate(&e));
@@ -306,9 +309,11 @@ static int run_steps_timed(qsim_plan *p, qsim_state *s, double *ms, int32_t *kin
     return rc;
 }
 
-static int run_steps(qsim_plan *p, qsim_state *s)
+static int run_steps(qsim_plan *p, qsim_state *s, bool from_zero = false)
 {
-    if (p->staged) return staged_execute(p->staged, s);
+    if (p->staged) return staged_execute(p->staged, s, from_zero);
+    if (from_zero)
+        if (int rc = launch_set_basis(s, 0)) return rc;
     for (const Step &st : p->steps) {
         int rc;
         if (st.type == 0)
@@ -427,11 +432,34 @@ int qsim_plan_execute(qsim_plan *p, qsim_state *s)
     return QSIM_OK;
 }
 
-int qsim_plan_execute_timed(qsim_plan *p, qsim_state *s, double *launch_ms, int32_t *kind, int32_t *fused_k)
+int qsim_plan_launches(const qsim_plan *p, int32_t *kind, int32_t *variant)
+{
+    if (!p) return set_error(QSIM_EINVAL, "null argument");
+    if (p->staged) {
+        for (int64_t i = 0; kind && i < p->info.launches; ++i) kind[i] = QSIM_KERNEL_STAGED;
+        if (variant) staged_launch_variants(p->staged, variant);
+        return QSIM_OK;
+    }
+    for (size_t i = 0; i < p->steps.size(); ++i) {
+        if (kind) kind[i] = kernel_kind(p->steps[i]);
+        if (variant) variant[i] = p->steps[i].type == 1 ? p->steps[i].k : 0;
+    }
+    return QSIM_OK;
+}
+
+int qsim_plan_execute_from_zero(qsim_plan *p, qsim_state *s)
 {
     if (!p || !s || !s->data) return set_error(QSIM_EINVAL, "null argument");
     if (p->n != s->n || p->dtype != s->dtype) return set_error(QSIM_EINVAL, "plan and state differ in n or dtype");
-    return run_steps_timed(p, s, launch_ms, kind, fused_k);
+    return run_steps(p, s, true);
+}
+
+int qsim_plan_execute_timed(qsim_plan *p, qsim_state *s, int from_zero, double *launch_ms, int32_t *kind,
+                            int32_t *fused_k)
+{
+    if (!p || !s || !s->data) return set_error(QSIM_EINVAL, "null argument");
+    if (p->n != s->n || p->dtype != s->dtype) return set_error(QSIM_EINVAL, "plan and state differ in n or dtype");
+    return run_steps_timed(p, s, from_zero != 0, launch_ms, kind, fused_k);
 }
 
 int qsim_plan_tune(int n, int dtype, const qsim_gate *gates, int64_t ngates, qsim_state *scratch, int reps,

@@ -99,7 +99,18 @@ struct Mat2 {
 // ---------------------------------------------------------------------------------------------
 // Kernel launchers (sweep kernels): all asynchronous on `st`
 // ---------------------------------------------------------------------------------------------
-enum class DiagMode : int { Values = 0, Angles = 1 };
+// Values: the factors are given; Angles: factor e^{i c} for each angle c, sin and cos in FP64 on the
+// device; Pow2: a phase factor e^{i s 2 pi / 2^k} with s = c[0] (+1 or -1) and k = c[1], the angle
+// itself formed on the device in FP64 (an exact power-of-two scaling of the FP64 value of 2 pi)
+enum class DiagMode : int { Values = 0, Angles = 1, Pow2 = 2 };
+
+// the FP64 value of 2 pi (the double nearest to it)
+constexpr double kTwoPi = 6.283185307179586;
+
+// ops whose only effect is the phase factor diag(1, e^{i theta}) on the target
+inline bool phase_op(int op) { return op == QSIM_OP_PHASE || op == QSIM_OP_RK || op == QSIM_OP_RKDG; }
+// theta of a phase op, in FP64 on the host (where gates are multiplied into fused matrices)
+double phase_angle(const qsim_gate &g);
 
 // general 2x2 on target (controls in map.set); map positions = sorted(controls U {target})
 int launch_general(qsim_state *s, const IndexMap &map, int target, const Mat2 &u);

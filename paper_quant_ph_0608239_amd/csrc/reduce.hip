@@ -3,6 +3,8 @@
 //   <Q_q> = sum_k |a_k|^2 bit_q(k) (Eq. Shor7), renormalisation, and inverse-CDF sampling.
 // Every reduction uses a grid fixed by the state size and fixed-order tree sums, so results are
 // deterministic run to run.
+#include <type_traits>
+
 #include "qsim_internal.h"
 
 namespace qsim {
@@ -39,7 +41,12 @@ template <typename T> __device__ __forceinline__ double sq(T r, T i)
     return x * x + y * y;
 }
 
-// grid-stride partial sums of |a|^2; amplitudes read as pairs of 16-byte words
+typedef double d2v __attribute__((ext_vector_type(2)));
+typedef float f4v __attribute__((ext_vector_type(4)));
+constexpr int kScaleWords = 4;
+
+// grid-stride partial sums of |a|^2; every lane reads 16-byte words (one complex128 amplitude or two
+// complex64 ones) with nontemporal loads (a state far larger than the caches is streamed once)
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_norm_partial(const T *__restrict__ a, uint64_t namps, double *__restrict__ partial)
 {
@@ -47,13 +54,13 @@ __global__ __launch_bounds__(kBlock) void k_norm_partial(const T *__restrict__ a
     double acc = 0.0;
     if constexpr (sizeof(T) == 8) {
         for (uint64_t i = uint64_t(blockIdx.x) * kBlock + threadIdx.x; i < namps; i += uint64_t(gridDim.x) * kBlock) {
-            const double2 v = reinterpret_cast<const double2 *>(a)[i];
+            const d2v v = __builtin_nontemporal_load(reinterpret_cast<const d2v *>(a) + i);
             acc += sq(v.x, v.y);
         }
     } else {
         const uint64_t nq = namps / 2;
         for (uint64_t i = uint64_t(blockIdx.x) * kBlock + threadIdx.x; i < nq; i += uint64_t(gridDim.x) * kBlock) {
-            const float4 v = reinterpret_cast<const float4 *>(a)[i];
+            const f4v v = __builtin_nontemporal_load(reinterpret_cast<const f4v *>(a) + i);
             acc += sq(v.x, v.y) + sq(v.z, v.w);
         }
         if (namps % 2 && blockIdx.x == 0 && threadIdx.x == 0) acc += sq(a[2 * (namps - 1)], a[2 * (namps - 1) + 1]);
@@ -141,22 +148,37 @@ __global__ __launch_bounds__(kBlock) void k_marg_partial(const T *__restrict__ a
 
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_scale(T *__restrict__ a, uint64_t namps, const double *__restrict__ factor_src,
-                                                 int mode)
+                                                 int mode, double *__restrict__ norm_out)
 {
-    // mode 0: factor = factor_src[0]; mode 1: factor = 1 / sqrt(factor_src[0]) (FP64)
-    const double f64 = mode ? 1.0 / sqrt(factor_src[0]) : factor_src[0];
+    // mode 0: factor = factor_src[0]; mode 1: factor = 1 / sqrt(factor_src[0]) (FP64); mode 2: the same
+    // when factor_src[0] > 0 and 1 (the state is left as it is) otherwise. norm_out (may be NULL)
+    // receives factor_src[0]. Lanes move 16-byte words with nontemporal loads and stores.
+    const double src = factor_src[0];
+    const double f64 = mode == 0 ? src : (mode == 2 && !(src > 0.0)) ? 1.0 : 1.0 / sqrt(src);
+    if (norm_out && blockIdx.x == 0 && threadIdx.x == 0) *norm_out = src;
     const T f = static_cast<T>(f64);
-    for (uint64_t i = uint64_t(blockIdx.x) * kBlock + threadIdx.x; i < namps; i += uint64_t(gridDim.x) * kBlock) {
-        if constexpr (sizeof(T) == 8) {
-            double2 v = reinterpret_cast<double2 *>(a)[i];
-            v.x *= f;
-            v.y *= f;
-            reinterpret_cast<double2 *>(a)[i] = v;
-        } else {
-            float2 v = reinterpret_cast<float2 *>(a)[i];
-            v.x *= f;
-            v.y *= f;
-            reinterpret_cast<float2 *>(a)[i] = v;
+    // each lane keeps kScaleWords 16-byte loads in flight before it multiplies and stores them
+    using W = typename std::conditional<sizeof(T) == 8, d2v, f4v>::type;
+    const uint64_t nw = sizeof(T) == 8 ? namps : namps / 2;
+    W *aw = reinterpret_cast<W *>(a);
+    const uint64_t step = uint64_t(gridDim.x) * kBlock * kScaleWords;
+    for (uint64_t b = uint64_t(blockIdx.x) * kBlock * kScaleWords + threadIdx.x; b < nw; b += step) {
+        W v[kScaleWords];
+#pragma unroll
+        for (int k = 0; k < kScaleWords; ++k)
+            if (b + uint64_t(k) * kBlock < nw) v[k] = __builtin_nontemporal_load(aw + b + uint64_t(k) * kBlock);
+#pragma unroll
+        for (int k = 0; k < kScaleWords; ++k) {
+            if (b + uint64_t(k) * kBlock < nw) {
+                v[k] *= f;
+                __builtin_nontemporal_store(v[k], aw + b + uint64_t(k) * kBlock);
+            }
+        }
+    }
+    if constexpr (sizeof(T) == 4) {
+        if (namps % 2 && blockIdx.x == 0 && threadIdx.x == 0) {
+            a[2 * (namps - 1)] *= f;
+            a[2 * (namps - 1) + 1] *= f;
         }
     }
 }
@@ -281,9 +303,11 @@ int launch_scale(qsim_state *s, const double *dev_factor)
     const uint64_t N = dim(s->n);
     const unsigned g = reduce_grid(N);
     if (s->dtype == QSIM_C128)
-        hipLaunchKernelGGL(k_scale<double>, dim3(g), dim3(kBlock), 0, s->stream, static_cast<double *>(s->data), N, dev_factor, 0);
+        hipLaunchKernelGGL(k_scale<double>, dim3(g), dim3(kBlock), 0, s->stream, static_cast<double *>(s->data), N, dev_factor, 0,
+                           nullptr);
     else
-        hipLaunchKernelGGL(k_scale<float>, dim3(g), dim3(kBlock), 0, s->stream, static_cast<float *>(s->data), N, dev_factor, 0);
+        hipLaunchKernelGGL(k_scale<float>, dim3(g), dim3(kBlock), 0, s->stream, static_cast<float *>(s->data), N, dev_factor, 0,
+                           nullptr);
     QSIM_HIP(hipGetLastError());
     return QSIM_OK;
 }
@@ -300,37 +324,58 @@ int run_renormalize(qsim_state *s, double *norm_before)
     const unsigned g = reduce_grid(N);
     // factor 1/sqrt(norm) evaluated in FP64 on the device from the norm left in scratch[0]
     if (s->dtype == QSIM_C128)
-        hipLaunchKernelGGL(k_scale<double>, dim3(g), dim3(kBlock), 0, s->stream, static_cast<double *>(s->data), N, s->scratch, 1);
+        hipLaunchKernelGGL(k_scale<double>, dim3(g), dim3(kBlock), 0, s->stream, static_cast<double *>(s->data), N, s->scratch, 1,
+                           nullptr);
     else
-        hipLaunchKernelGGL(k_scale<float>, dim3(g), dim3(kBlock), 0, s->stream, static_cast<float *>(s->data), N, s->scratch, 1);
+        hipLaunchKernelGGL(k_scale<float>, dim3(g), dim3(kBlock), 0, s->stream, static_cast<float *>(s->data), N, s->scratch, 1,
+                           nullptr);
     QSIM_HIP(hipGetLastError());
     QSIM_HIP(hipStreamSynchronize(s->stream));
     if (norm_before) *norm_before = nrm;
     return QSIM_OK;
 }
 
+namespace {
+// device buffers of one sampling call: freed on every return path, after the state's stream has
+// drained (a failed call may still have work in flight that reads them)
+struct SampleBuffers {
+    hipStream_t stream = nullptr;
+    double *sums = nullptr, *rem = nullptr;
+    uint64_t *chunk = nullptr, *out = nullptr;
+    ~SampleBuffers()
+    {
+        if (sums || rem || chunk || out) (void)hipStreamSynchronize(stream);
+        if (sums) (void)hipFree(sums);
+        if (rem) (void)hipFree(rem);
+        if (chunk) (void)hipFree(chunk);
+        if (out) (void)hipFree(out);
+    }
+};
+}  // namespace
+
 int run_sample(qsim_state *s, int64_t shots, const double *uniforms, uint64_t *out)
 {
     // two levels: FP64 sums over fixed chunks of 2^c amplitudes (device), a cumulative walk over the
     // chunk sums per shot (host, FP64, in index order), then the walk inside the chosen chunk (device)
+    for (int64_t i = 0; i < shots; ++i)
+        if (!(uniforms[i] >= 0.0 && uniforms[i] < 1.0)) return set_error(QSIM_EINVAL, "sample: uniforms must lie in [0, 1)");
     const int n = s->n;
     const int c = n > 12 ? 12 : n;
     const uint64_t chunk = uint64_t(1) << c;
     const uint64_t nchunks = dim(n) >> c;
     std::vector<double> sums(nchunks);
-    double *dsums = nullptr;
-    uint64_t *dchunk = nullptr, *dout = nullptr;
-    double *drem = nullptr;
-    QSIM_HIP(hipMalloc((void **)&dsums, sizeof(double) * nchunks));
+    SampleBuffers b;
+    b.stream = s->stream;
+    QSIM_HIP(hipMalloc((void **)&b.sums, sizeof(double) * nchunks));
     const unsigned g = unsigned(nchunks < 8192 ? nchunks : 8192);
     if (s->dtype == QSIM_C128)
         hipLaunchKernelGGL(k_chunk_sums<double>, dim3(g), dim3(kBlock), 0, s->stream, static_cast<const double *>(s->data), chunk,
-                           nchunks, dsums);
+                           nchunks, b.sums);
     else
         hipLaunchKernelGGL(k_chunk_sums<float>, dim3(g), dim3(kBlock), 0, s->stream, static_cast<const float *>(s->data), chunk,
-                           nchunks, dsums);
+                           nchunks, b.sums);
     QSIM_HIP(hipGetLastError());
-    QSIM_HIP(hipMemcpyAsync(sums.data(), dsums, sizeof(double) * nchunks, hipMemcpyDeviceToHost, s->stream));
+    QSIM_HIP(hipMemcpyAsync(sums.data(), b.sums, sizeof(double) * nchunks, hipMemcpyDeviceToHost, s->stream));
     QSIM_HIP(hipStreamSynchronize(s->stream));
     double total = 0.0;
     for (double v : sums) total += v;
@@ -343,12 +388,7 @@ int run_sample(qsim_state *s, int64_t shots, const double *uniforms, uint64_t *o
     std::vector<uint64_t> sc(shots);
     std::vector<double> rem(shots);
     for (int64_t i = 0; i < shots; ++i) {
-        const double u = uniforms[i];
-        if (!(u >= 0.0 && u < 1.0)) {
-            (void)hipFree(dsums);
-            return set_error(QSIM_EINVAL, "sample: uniforms must lie in [0, 1)");
-        }
-        const double target = u * total;
+        const double target = uniforms[i] * total;
         uint64_t lo = 0, hi = nchunks - 1;  // first chunk with cum > target
         while (lo < hi) {
             const uint64_t mid = (lo + hi) / 2;
@@ -359,25 +399,21 @@ int run_sample(qsim_state *s, int64_t shots, const double *uniforms, uint64_t *o
         sc[i] = lo;
         rem[i] = target - (lo ? cum[lo - 1] : 0.0);
     }
-    QSIM_HIP(hipMalloc((void **)&dchunk, sizeof(uint64_t) * shots));
-    QSIM_HIP(hipMalloc((void **)&drem, sizeof(double) * shots));
-    QSIM_HIP(hipMalloc((void **)&dout, sizeof(uint64_t) * shots));
-    QSIM_HIP(hipMemcpyAsync(dchunk, sc.data(), sizeof(uint64_t) * shots, hipMemcpyHostToDevice, s->stream));
-    QSIM_HIP(hipMemcpyAsync(drem, rem.data(), sizeof(double) * shots, hipMemcpyHostToDevice, s->stream));
+    QSIM_HIP(hipMalloc((void **)&b.chunk, sizeof(uint64_t) * shots));
+    QSIM_HIP(hipMalloc((void **)&b.rem, sizeof(double) * shots));
+    QSIM_HIP(hipMalloc((void **)&b.out, sizeof(uint64_t) * shots));
+    QSIM_HIP(hipMemcpyAsync(b.chunk, sc.data(), sizeof(uint64_t) * shots, hipMemcpyHostToDevice, s->stream));
+    QSIM_HIP(hipMemcpyAsync(b.rem, rem.data(), sizeof(double) * shots, hipMemcpyHostToDevice, s->stream));
     const unsigned gs = unsigned((shots + kBlock - 1) / kBlock);
     if (s->dtype == QSIM_C128)
         hipLaunchKernelGGL(k_sample_in_chunk<double>, dim3(gs), dim3(kBlock), 0, s->stream, static_cast<const double *>(s->data),
-                           chunk, dchunk, drem, shots, dout);
+                           chunk, b.chunk, b.rem, shots, b.out);
     else
         hipLaunchKernelGGL(k_sample_in_chunk<float>, dim3(gs), dim3(kBlock), 0, s->stream, static_cast<const float *>(s->data),
-                           chunk, dchunk, drem, shots, dout);
+                           chunk, b.chunk, b.rem, shots, b.out);
     QSIM_HIP(hipGetLastError());
-    QSIM_HIP(hipMemcpyAsync(out, dout, sizeof(uint64_t) * shots, hipMemcpyDeviceToHost, s->stream));
+    QSIM_HIP(hipMemcpyAsync(out, b.out, sizeof(uint64_t) * shots, hipMemcpyDeviceToHost, s->stream));
     QSIM_HIP(hipStreamSynchronize(s->stream));
-    (void)hipFree(dsums);
-    (void)hipFree(dchunk);
-    (void)hipFree(drem);
-    (void)hipFree(dout);
     return QSIM_OK;
 }
 

@@ -39,12 +39,12 @@ namespace {
 template <typename T, int LOG_E, int LOG_T, int MINW>
 __global__ __launch_bounds__(1 << LOG_T, MINW) void k_staged(T *__restrict__ a, const SPass *__restrict__ passp,
                                                              const SStage *__restrict__ stages, const SRound *__restrict__ rounds,
-                                                             const SOp *__restrict__ ops)
+                                                             const SOp *__restrict__ ops, int init_zero)
 {
     using C = typename Vec<T>::C;
     __shared__ C lds[lds_slots<T>(LOG_E + LOG_T)];
     const SPass pass = ldc<SPass>(as_const(passp));
-    run_block<T, LOG_E, LOG_T>(a, pass, blockIdx.x, as_const(stages), as_const(rounds), as_const(ops), lds, false);
+    run_block<T, LOG_E, LOG_T>(a, pass, blockIdx.x, as_const(stages), as_const(rounds), as_const(ops), lds, init_zero != 0);
 }
 
 // The same pass with a buffer of half the block (every LDS round trip in two halves): twice the
@@ -53,12 +53,13 @@ template <typename T, int LOG_E, int LOG_T, int MINW>
 __global__ __launch_bounds__(1 << LOG_T, MINW) void k_staged_half(T *__restrict__ a, const SPass *__restrict__ passp,
                                                                   const SStage *__restrict__ stages,
                                                                   const SRound *__restrict__ rounds,
-                                                                  const SOp *__restrict__ ops)
+                                                                  const SOp *__restrict__ ops, int init_zero)
 {
     using C = typename Vec<T>::C;
     __shared__ C lds[lds_slots<T>(LOG_E + LOG_T - 1)];
     const SPass pass = ldc<SPass>(as_const(passp));
-    run_block_half<T, LOG_E, LOG_T>(a, pass, blockIdx.x, as_const(stages), as_const(rounds), as_const(ops), lds);
+    run_block_half<T, LOG_E, LOG_T>(a, pass, blockIdx.x, as_const(stages), as_const(rounds), as_const(ops), lds,
+                                    init_zero != 0);
 }
 
 // The half-buffer pass when every split is at a wave position: uniform split branches, and the block
@@ -67,12 +68,13 @@ template <typename T, int LOG_E, int LOG_T, int MINW>
 __global__ __launch_bounds__(1 << LOG_T, MINW) void k_staged_wave(T *__restrict__ a, const SPass *__restrict__ passp,
                                                                   const SStage *__restrict__ stages,
                                                                   const SRound *__restrict__ rounds,
-                                                                  const SOp *__restrict__ ops)
+                                                                  const SOp *__restrict__ ops, int init_zero)
 {
     using C = typename Vec<T>::C;
     __shared__ C lds[lds_slots<T>(LOG_E + LOG_T - 1)];
     const SPass pass = ldc<SPass>(as_const(passp));
-    run_block_wave<T, LOG_E, LOG_T>(a, pass, blockIdx.x, as_const(stages), as_const(rounds), as_const(ops), lds);
+    run_block_wave<T, LOG_E, LOG_T>(a, pass, blockIdx.x, as_const(stages), as_const(rounds), as_const(ops), lds,
+                                    init_zero != 0);
 }
 
 }  // namespace
@@ -85,10 +87,12 @@ __global__ void k_op_angles(SOp *ops, int nops)
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= nops) return;
     SOp &op = ops[i];
-    if (op.angles == 1) {
+    if (op.angles == 1 || op.angles == 3) {
+        // 3: theta = s 2 pi / 2^k with s = theta[0], k = theta[1], an exact scaling of FP64 2 pi
+        const double th = op.angles == 3 ? op.theta[0] * ldexp(kTwoPi, -int(op.theta[1])) : op.theta[0];
         op.m[0] = 1.0;
         op.m[1] = 0.0;
-        sincos(op.theta[0], &op.m[3], &op.m[2]);
+        sincos(th, &op.m[3], &op.m[2]);
     } else if (op.angles == 2) {
         sincos(op.theta[0], &op.m[1], &op.m[0]);
         sincos(op.theta[1], &op.m[3], &op.m[2]);
@@ -141,6 +145,13 @@ GInfo describe(const qsim_gate &g)
         d.kind = G_PHASE;
         d.angles = 1;
         d.theta[0] = g.theta;
+        return d;
+    }
+    if (g.op == QSIM_OP_RK || g.op == QSIM_OP_RKDG) {  // the angle s 2 pi / 2^k is formed on the device
+        d.kind = G_PHASE;
+        d.angles = 3;
+        d.theta[0] = g.op == QSIM_OP_RK ? 1.0 : -1.0;
+        d.theta[1] = double(g.target2);
         return d;
     }
     if (g.op == QSIM_OP_RZ) {
@@ -397,7 +408,7 @@ static void emit_stage(SStage cur, uint32_t rbset, int log_e, int m, int dtype, 
             const bool cond = o.lcm_t != 0 || rsel != 0 || o.gcm != 0 || !rc;
             key[xi] = kLists * j + (cond ? kListCond : 0);
         } else {
-            const bool d0_one = h.angles == 1 || (h.angles == 0 && h.m[0] == 1.0 && h.m[1] == 0.0);
+            const bool d0_one = h.angles == 1 || h.angles == 3 || (h.angles == 0 && h.m[0] == 1.0 && h.m[1] == 0.0);
             const int lt = localof[h.target];
             if (lt >= 0 && ((rbset >> lt) & 1)) {
                 const int jt = rank_of(lt);
@@ -944,49 +955,61 @@ int staged_build(int n, int dtype, const std::vector<qsim_gate> &gates, int lds_
 }
 
 template <typename T, int LE, int LT, int MW>
-static void launch_variant(StagedPlan *p, qsim_state *s, size_t i)
+static void launch_variant(StagedPlan *p, qsim_state *s, size_t i, int init_zero)
 {
     hipLaunchKernelGGL((k_staged<T, LE, LT, MW>), dim3(unsigned(dim(p->n - p->m))), dim3(1 << LT), 0, s->stream,
-                       static_cast<T *>(s->data), p->d_passes + i, p->d_stages, p->d_rounds, p->d_ops);
+                       static_cast<T *>(s->data), p->d_passes + i, p->d_stages, p->d_rounds, p->d_ops, init_zero);
 }
 
 template <typename T, int LE, int LT, int MW>
-static void launch_half(StagedPlan *p, qsim_state *s, size_t i)
+static void launch_half(StagedPlan *p, qsim_state *s, size_t i, int init_zero)
 {
     hipLaunchKernelGGL((k_staged_half<T, LE, LT, MW>), dim3(unsigned(dim(p->n - p->m))), dim3(1 << LT), 0, s->stream,
-                       static_cast<T *>(s->data), p->d_passes + i, p->d_stages, p->d_rounds, p->d_ops);
+                       static_cast<T *>(s->data), p->d_passes + i, p->d_stages, p->d_rounds, p->d_ops, init_zero);
 }
 
 template <typename T, int LE, int LT, int MW>
-static void launch_wave(StagedPlan *p, qsim_state *s, size_t i)
+static void launch_wave(StagedPlan *p, qsim_state *s, size_t i, int init_zero)
 {
     hipLaunchKernelGGL((k_staged_wave<T, LE, LT, MW>), dim3(unsigned(dim(p->n - p->m))), dim3(1 << LT), 0, s->stream,
-                       static_cast<T *>(s->data), p->d_passes + i, p->d_stages, p->d_rounds, p->d_ops);
+                       static_cast<T *>(s->data), p->d_passes + i, p->d_stages, p->d_rounds, p->d_ops, init_zero);
 }
 
-static int launch_pass(StagedPlan *p, qsim_state *s, size_t i)
+// the kernel that runs pass i: the wave-split kernel where every round trip splits at a wave position
+// and the block shape has one, the half-buffer kernel where every round trip splits, else the full one
+static int pass_variant(const StagedPlan *p, size_t i)
 {
     const int v = p->log_e * 16 + p->log_t;
-    if ((p->passes[i].direct & 12) == 12 && p->dtype == QSIM_C128 && (v == 4 * 16 + 7 || v == 4 * 16 + 8)) {
-        if (v == 4 * 16 + 7) launch_wave<double, 4, 7, 4>(p, s, i);
-        else launch_wave<double, 4, 8, 4>(p, s, i);
+    const int d = p->passes[i].direct;
+    if ((d & 12) == 12 && p->dtype == QSIM_C128 && (v == 4 * 16 + 7 || v == 4 * 16 + 8)) return QSIM_STAGED_WAVE;
+    if ((d & 12) == 12 && p->dtype == QSIM_C64 && (v == 5 * 16 + 7 || v == 5 * 16 + 8)) return QSIM_STAGED_WAVE;
+    return (d & 4) ? QSIM_STAGED_HALF : QSIM_STAGED_FULL;
+}
+
+static int launch_pass(StagedPlan *p, qsim_state *s, size_t i, int init_zero)
+{
+    const int v = p->log_e * 16 + p->log_t;
+    const int var = pass_variant(p, i);
+    if (var == QSIM_STAGED_WAVE && p->dtype == QSIM_C128) {
+        if (v == 4 * 16 + 7) launch_wave<double, 4, 7, 4>(p, s, i, init_zero);
+        else launch_wave<double, 4, 8, 4>(p, s, i, init_zero);
         QSIM_HIP(hipGetLastError());
         return QSIM_OK;
     }
-    if ((p->passes[i].direct & 12) == 12 && p->dtype == QSIM_C64 && (v == 5 * 16 + 7 || v == 5 * 16 + 8)) {
-        if (v == 5 * 16 + 7) launch_wave<float, 5, 7, 4>(p, s, i);
-        else launch_wave<float, 5, 8, 4>(p, s, i);
+    if (var == QSIM_STAGED_WAVE) {
+        if (v == 5 * 16 + 7) launch_wave<float, 5, 7, 4>(p, s, i, init_zero);
+        else launch_wave<float, 5, 8, 4>(p, s, i, init_zero);
         QSIM_HIP(hipGetLastError());
         return QSIM_OK;
     }
-    if (p->passes[i].direct & 4) {
+    if (var == QSIM_STAGED_HALF) {
         switch ((p->dtype == QSIM_C128 ? 256 : 0) + v) {
-        case 256 + 4 * 16 + 6: launch_half<double, 4, 6, 3>(p, s, i); break;
-        case 256 + 4 * 16 + 7: launch_half<double, 4, 7, 3>(p, s, i); break;
-        case 256 + 4 * 16 + 8: launch_half<double, 4, 8, 3>(p, s, i); break;
-        case 5 * 16 + 6: launch_half<float, 5, 6, 3>(p, s, i); break;
-        case 5 * 16 + 7: launch_half<float, 5, 7, 3>(p, s, i); break;
-        case 5 * 16 + 8: launch_half<float, 5, 8, 3>(p, s, i); break;
+        case 256 + 4 * 16 + 6: launch_half<double, 4, 6, 3>(p, s, i, init_zero); break;
+        case 256 + 4 * 16 + 7: launch_half<double, 4, 7, 3>(p, s, i, init_zero); break;
+        case 256 + 4 * 16 + 8: launch_half<double, 4, 8, 3>(p, s, i, init_zero); break;
+        case 5 * 16 + 6: launch_half<float, 5, 6, 3>(p, s, i, init_zero); break;
+        case 5 * 16 + 7: launch_half<float, 5, 7, 3>(p, s, i, init_zero); break;
+        case 5 * 16 + 8: launch_half<float, 5, 8, 3>(p, s, i, init_zero); break;
         default: return set_error(QSIM_EINVAL, "staged: no half-buffer kernel for this block shape");
         }
         QSIM_HIP(hipGetLastError());
@@ -994,38 +1017,44 @@ static int launch_pass(StagedPlan *p, qsim_state *s, size_t i)
     }
     if (p->dtype == QSIM_C128) {
         switch (v) {
-        case 3 * 16 + 7: launch_variant<double, 3, 7, 4>(p, s, i); break;
-        case 3 * 16 + 8: launch_variant<double, 3, 8, 4>(p, s, i); break;
-        case 3 * 16 + 9: launch_variant<double, 3, 9, 3>(p, s, i); break;
-        case 4 * 16 + 6: launch_variant<double, 4, 6, 2>(p, s, i); break;
-        case 4 * 16 + 7: launch_variant<double, 4, 7, 2>(p, s, i); break;
-        case 4 * 16 + 9: launch_variant<double, 4, 9, 2>(p, s, i); break;  // 13 resident qubits, one workgroup per CU
-        default: launch_variant<double, 4, 8, 2>(p, s, i); break;
+        case 3 * 16 + 7: launch_variant<double, 3, 7, 4>(p, s, i, init_zero); break;
+        case 3 * 16 + 8: launch_variant<double, 3, 8, 4>(p, s, i, init_zero); break;
+        case 3 * 16 + 9: launch_variant<double, 3, 9, 3>(p, s, i, init_zero); break;
+        case 4 * 16 + 6: launch_variant<double, 4, 6, 2>(p, s, i, init_zero); break;
+        case 4 * 16 + 7: launch_variant<double, 4, 7, 2>(p, s, i, init_zero); break;
+        case 4 * 16 + 9: launch_variant<double, 4, 9, 2>(p, s, i, init_zero); break;  // 13 resident qubits, one workgroup per CU
+        default: launch_variant<double, 4, 8, 2>(p, s, i, init_zero); break;
         }
     } else {
         switch (v) {
-        case 4 * 16 + 7: launch_variant<float, 4, 7, 3>(p, s, i); break;
-        case 4 * 16 + 8: launch_variant<float, 4, 8, 3>(p, s, i); break;
-        case 4 * 16 + 9: launch_variant<float, 4, 9, 2>(p, s, i); break;
-        case 5 * 16 + 6: launch_variant<float, 5, 6, 1>(p, s, i); break;
-        case 5 * 16 + 7: launch_variant<float, 5, 7, 1>(p, s, i); break;
-        case 5 * 16 + 9: launch_variant<float, 5, 9, 1>(p, s, i); break;   // 14 resident qubits, one workgroup per CU
-        case 4 * 16 + 10: launch_variant<float, 4, 10, 4>(p, s, i); break; // 14 resident qubits, 1024 threads
-        default: launch_variant<float, 5, 8, 1>(p, s, i); break;
+        case 4 * 16 + 7: launch_variant<float, 4, 7, 3>(p, s, i, init_zero); break;
+        case 4 * 16 + 8: launch_variant<float, 4, 8, 3>(p, s, i, init_zero); break;
+        case 4 * 16 + 9: launch_variant<float, 4, 9, 2>(p, s, i, init_zero); break;
+        case 5 * 16 + 6: launch_variant<float, 5, 6, 1>(p, s, i, init_zero); break;
+        case 5 * 16 + 7: launch_variant<float, 5, 7, 1>(p, s, i, init_zero); break;
+        case 5 * 16 + 9: launch_variant<float, 5, 9, 1>(p, s, i, init_zero); break;   // 14 resident qubits, one workgroup per CU
+        case 4 * 16 + 10: launch_variant<float, 4, 10, 4>(p, s, i, init_zero); break; // 14 resident qubits, 1024 threads
+        default: launch_variant<float, 5, 8, 1>(p, s, i, init_zero); break;
         }
     }
     QSIM_HIP(hipGetLastError());
     return QSIM_OK;
 }
 
-int staged_execute(StagedPlan *p, qsim_state *s)
+void staged_launch_variants(const StagedPlan *p, int32_t *variant)
+{
+    for (size_t i = 0; i < p->passes.size(); ++i) variant[i] = pass_variant(p, i);
+}
+
+// from_zero: the first pass generates |0...0> in its loads instead of reading the state
+int staged_execute(StagedPlan *p, qsim_state *s, bool from_zero)
 {
     for (size_t i = 0; i < p->passes.size(); ++i)
-        if (int rc = launch_pass(p, s, i)) return rc;
+        if (int rc = launch_pass(p, s, i, from_zero && i == 0)) return rc;
     return QSIM_OK;
 }
 
-int staged_execute_timed(StagedPlan *p, qsim_state *s, double *ms, int32_t *kind, int32_t *fk)
+int staged_execute_timed(StagedPlan *p, qsim_state *s, bool from_zero, double *ms, int32_t *kind, int32_t *fk)
 {
     const size_t L = p->passes.size();
     std::vector<hipEvent_t> ev(2 * L, nullptr);
@@ -1033,7 +1062,7 @@ int staged_execute_timed(StagedPlan *p, qsim_state *s, double *ms, int32_t *kind
     int rc = QSIM_OK;
     for (size_t i = 0; i < L && !rc; ++i) {
         QSIM_HIP(hipEventRecord(ev[2 * i], s->stream));
-        rc = launch_pass(p, s, i);
+        rc = launch_pass(p, s, i, from_zero && i == 0);
         QSIM_HIP(hipEventRecord(ev[2 * i + 1], s->stream));
     }
     if (!rc) {

@@ -21,7 +21,8 @@ struct SOp {
     uint64_t gtb;      // diag: the target's index bit when the target is not resident, else 0
     uint32_t m0, m1;   // diag: register elements r that take factor d0 / d1
     int32_t lt;        // diag: local bit of the target when it is a thread bit, else -1
-    int32_t angles;    // 0: m[] given; 1: d0 = 1, d1 = e^{i theta0}; 2: d0 = e^{i theta0}, d1 = e^{i theta1}
+    int32_t angles;    // 0: m[] given; 1: d0 = 1, d1 = e^{i theta0}; 2: d0 = e^{i theta0}, d1 = e^{i theta1};
+                       // 3: d0 = 1, d1 = e^{i theta0 2 pi / 2^theta1} (theta0 = +-1, theta1 = k)
     double m[8];       // dense: 2x2 row-major (re, im); diag: d0 = m[0..1], d1 = m[2..3]
     double theta[2];   // angle inputs of the angles != 0 forms
     float mf[8];       // m rounded to FP32 (complex64 kernels), filled on the device
@@ -702,7 +703,8 @@ __device__ __forceinline__ void exchange_half(typename Vec<T>::C *x, typename Ve
 // trip split in two by the stages' split bits. `lds` holds lds_slots<T>(LOG_E + LOG_T - 1) amplitudes.
 template <typename T, int LOG_E, int LOG_T>
 __device__ __forceinline__ void run_block_half(T *__restrict__ a, const SPass &pass, uint64_t blk, cptr<SStage> stages,
-                                               cptr<SRound> rounds, cptr<SOp> ops, typename Vec<T>::C *lds)
+                                               cptr<SRound> rounds, cptr<SOp> ops, typename Vec<T>::C *lds,
+                                               bool init_zero)
 {
     using C = typename Vec<T>::C;
     constexpr int E = 1 << LOG_E;
@@ -730,12 +732,16 @@ __device__ __forceinline__ void run_block_half(T *__restrict__ a, const SPass &p
 #pragma unroll
             for (int j = 0; j < LOG_E; ++j)
                 if ((r >> j) & 1) v |= uint64_t(1) << st.prb[j];
-            x[r] = ld_nt(ag + v);
+            x[r] = init_zero ? C{(gt | v) == 0 ? T(1) : T(0), T(0)} : ld_nt(ag + v);
         }
     } else {
-        const C *ag = reinterpret_cast<const C *>(a) + (base | lane_part<LOG_T>(pass, t));
+        const uint64_t g0 = base | lane_part<LOG_T>(pass, t);
+        const C *ag = reinterpret_cast<const C *>(a) + g0;
 #pragma unroll
-        for (int k = 0; k < E; ++k) x[k] = ld_nt(ag + elem_part<LOG_E, LOG_T>(pass, k));
+        for (int k = 0; k < E; ++k) {
+            const uint64_t ek = elem_part<LOG_E, LOG_T>(pass, k);
+            x[k] = init_zero ? C{(g0 | ek) == 0 ? T(1) : T(0), T(0)} : ld_nt(ag + ek);
+        }
         int so[E];
         half_slots<T, LOG_E>(st.rb, st.hb_in, so);
         exchange_half<T, E>(x, lds, slot<T>(int(squeeze(uint32_t(t), st.hb_in))), lso,
@@ -786,9 +792,20 @@ __device__ __forceinline__ void run_block_half(T *__restrict__ a, const SPass &p
 // one half, so the branches are uniform and each arm is straight-line code:
 //   first half:   [B0] write B1 read B2 B3
 //   second half:  [B0] B1 B2 write B3 read
-// Every wavefront passes the same barriers. The write half ends a stage and the read half starts the
-// next, so the amplitudes are not live across the stage loop; together with recomputing addresses and
-// thread bits where they are used, the block fits in 128 VGPRs (four 256-thread workgroups per CU).
+// The write half ends a stage and the read half starts the next, so the amplitudes are not live across
+// the stage loop; together with recomputing addresses and thread bits where they are used, the block
+// fits in 128 VGPRs (four 256-thread workgroups per CU).
+//
+// Barrier invariant. The barriers sit in branches that are uniform per wavefront (j >= 6 is a wave bit)
+// but differ between the halves. This is correct because s_barrier counts one arrival per wavefront:
+// the k-th barrier a wavefront executes is the same barrier instance for every wavefront, whichever
+// branch issued it. Every wavefront executes pre + 3 barriers per round trip (first half: pre, B1
+// after its write, B2 and B3 after its read; second half: pre, B1, B2 before its write, B3 after it),
+// and all wavefronts run the same round trips in the same order (they depend only on the uniform pass
+// and stage records). So B1 orders the first half's writes before its reads, B2 its reads before the
+// second half's writes, B3 those writes before the second half's reads, and the next round trip's
+// pre barrier orders the second half's reads before any new write. tests/staged_model.py follows this
+// control flow wavefront by wavefront and checks the counts and these orderings on real schedules.
 template <typename T, int E>
 __device__ __forceinline__ void wave_out(const typename Vec<T>::C *x, typename Vec<T>::C *lds, int wls, const int *wso,
                                          uint32_t j, bool pre)
@@ -820,7 +837,8 @@ __device__ __forceinline__ void wave_in(typename Vec<T>::C *x, const typename Ve
 // lds_slots<T>(LOG_E + LOG_T - 1) amplitudes.
 template <typename T, int LOG_E, int LOG_T>
 __device__ __forceinline__ void run_block_wave(T *__restrict__ a, const SPass &pass, uint64_t blk, cptr<SStage> stages,
-                                               cptr<SRound> rounds, cptr<SOp> ops, typename Vec<T>::C *lds)
+                                               cptr<SRound> rounds, cptr<SOp> ops, typename Vec<T>::C *lds,
+                                               bool init_zero)
 {
     using C = typename Vec<T>::C;
     constexpr int E = 1 << LOG_E;
@@ -850,7 +868,7 @@ __device__ __forceinline__ void run_block_wave(T *__restrict__ a, const SPass &p
 #pragma unroll
                 for (int j = 0; j < LOG_E; ++j)
                     if ((r >> j) & 1) v |= uint64_t(1) << st.prb[j];
-                x[r] = ld_nt(ag + v);
+                x[r] = init_zero ? C{(gt | v) == 0 ? T(1) : T(0), T(0)} : ld_nt(ag + v);
             }
         } else {
             if (first) {
@@ -858,7 +876,10 @@ __device__ __forceinline__ void run_block_wave(T *__restrict__ a, const SPass &p
                 asm volatile("" : "+v"(g0));  // not kept alive until the store
                 const C *ag = reinterpret_cast<const C *>(a) + g0;
 #pragma unroll
-                for (int k = 0; k < E; ++k) x[k] = ld_nt(ag + elem_part<LOG_E, LOG_T>(pass, k));
+                for (int k = 0; k < E; ++k) {
+                    const uint64_t ek = elem_part<LOG_E, LOG_T>(pass, k);
+                    x[k] = init_zero ? C{(g0 | ek) == 0 ? T(1) : T(0), T(0)} : ld_nt(ag + ek);
+                }
                 wave_out<T, E>(x, lds, slot<T>(int(squeeze(uint32_t(t), st.hb_in))), lso, st.hj_in, false);
             }
             int so[E];

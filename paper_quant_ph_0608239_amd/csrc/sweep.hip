@@ -245,6 +245,7 @@ __device__ __forceinline__ void k_phase_body(T *__restrict__ a, uint64_t items, 
     using C = typename Vec<T>::C;
     using C2 = typename Vec<T>::C2;
     double fr64 = c0, fi64 = c1;
+    if (angle_mode == int(DiagMode::Pow2)) c0 = c0 * ldexp(kTwoPi, -int(c1));  // theta = s 2 pi / 2^k, FP64
     if (angle_mode) sincos(c0, &fi64, &fr64);  // FP64 phase factor e^{i theta}
     const T fr = static_cast<T>(fr64), fi = static_cast<T>(fi64);
     const uint64_t chunk = uint64_t(kBlock) * ITEMS;
@@ -393,10 +394,13 @@ __global__ __launch_bounds__(kBlock) void k_set_basis(T *__restrict__ a, uint64_
 
 // Powers f(x) = y^x mod G for x < count by square and multiply (G < 2^32, so every product of two
 // residues fits 64 bits).
-__global__ __launch_bounds__(kBlock) void k_powmod_table(uint32_t *__restrict__ f, uint64_t count, uint64_t y, uint64_t G)
+// Powers y^(x * stride) mod G for x < count (square and multiply; G < 2^32, so every product of two
+// residues fits in 64 bits).
+__global__ __launch_bounds__(kBlock) void k_powmod_table(uint32_t *__restrict__ f, uint64_t count, uint64_t y,
+                                                        uint64_t stride, uint64_t G)
 {
     for (uint64_t x = uint64_t(blockIdx.x) * kBlock + threadIdx.x; x < count; x += uint64_t(gridDim.x) * kBlock) {
-        uint64_t r = 1 % G, b = y % G, e = x;
+        uint64_t r = 1 % G, b = y % G, e = x * stride;
         while (e) {
             if (e & 1) r = r * b % G;
             b = b * b % G;
@@ -406,16 +410,31 @@ __global__ __launch_bounds__(kBlock) void k_powmod_table(uint32_t *__restrict__ 
     }
 }
 
-// |x>|z> -> |x>|z XOR f(x)>: a permutation of basis states made of disjoint exchanges; the thread of
-// the smaller index of each exchanged pair moves both amplitudes (no arithmetic, bit-exact).
+// a * b mod G for residues a, b < G < 2^32 by Barrett reduction with minv = floor((2^64 - 1) / G):
+// the estimated quotient is at most two below the true one, so at most two corrections follow
+__device__ __forceinline__ uint64_t mulmod(uint64_t a, uint64_t b, uint64_t G, uint64_t minv)
+{
+    const uint64_t p = a * b;
+    uint64_t r = p - __umul64hi(p, minv) * G;
+    if (r >= G) r -= G;
+    if (r >= G) r -= G;
+    return r;
+}
+
+// |x>|z> -> |x>|z XOR f(x)>, f(x) = y^x mod G = lo[x mod 2^h] * hi[x >> h] mod G: a permutation of
+// basis states made of disjoint exchanges; the thread of the smaller index of each exchanged pair moves
+// both amplitudes (no arithmetic on them, bit-exact).
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_xor_permute(T *__restrict__ a, uint64_t namps, const uint32_t *__restrict__ f,
-                                                        int x_first, uint64_t xmask, int f_first)
+__global__ __launch_bounds__(kBlock) void k_xor_permute(T *__restrict__ a, uint64_t namps, const uint32_t *__restrict__ lo,
+                                                        const uint32_t *__restrict__ hi, int x_first, uint64_t xmask, int h,
+                                                        int f_first, uint64_t G, uint64_t minv)
 {
     using C = typename Vec<T>::C;
     C *ac = reinterpret_cast<C *>(a);
+    const uint64_t lomask = (uint64_t(1) << h) - 1;
     for (uint64_t i = uint64_t(blockIdx.x) * kBlock + threadIdx.x; i < namps; i += uint64_t(gridDim.x) * kBlock) {
-        const uint64_t v = f[(i >> x_first) & xmask];
+        const uint64_t x = (i >> x_first) & xmask;
+        const uint64_t v = mulmod(lo[x & lomask], hi[x >> h], G, minv);
         const uint64_t j = i ^ (v << f_first);
         if (j <= i) continue;
         const C ai = ac[i], aj = ac[j];
@@ -620,24 +639,26 @@ int launch_swap(qsim_state *s, const IndexMap &map, uint64_t flip)
 
 int launch_modexp(qsim_state *s, int x_first, int x_qubits, int f_first, uint64_t y, uint64_t G)
 {
-    const uint64_t X = uint64_t(1) << x_qubits;
-    uint32_t *f = nullptr;
-    QSIM_HIP(hipMalloc(&f, X * sizeof(uint32_t)));
-    hipLaunchKernelGGL(k_powmod_table, dim3(grid_for(X, kBlock)), dim3(kBlock), 0, s->stream, f, X, y, G);
-    hipError_t e = hipGetLastError();
+    // two power tables in the state's scratch buffer: y^xl for the low h bits of x and y^(xh 2^h) for
+    // the high ones (at most 2 * 2^15 entries for a 30-qubit x-register); no allocation, no host wait
+    const int h = (x_qubits + 1) / 2;
+    const uint64_t nlo = uint64_t(1) << h, nhi = uint64_t(1) << (x_qubits - h);
+    static_assert(2 * (1 << 15) * sizeof(uint32_t) <= kScratchDoubles * sizeof(double), "power tables fit the scratch");
+    uint32_t *lo = reinterpret_cast<uint32_t *>(s->scratch);
+    uint32_t *hi = lo + nlo;
+    const uint64_t minv = ~uint64_t(0) / G;
+    hipLaunchKernelGGL(k_powmod_table, dim3(grid_for(nlo, kBlock)), dim3(kBlock), 0, s->stream, lo, nlo, y, uint64_t(1), G);
+    hipLaunchKernelGGL(k_powmod_table, dim3(grid_for(nhi, kBlock)), dim3(kBlock), 0, s->stream, hi, nhi, y, nlo, G);
+    QSIM_HIP(hipGetLastError());
     const uint64_t N = dim(s->n);
-    if (e == hipSuccess) {
-        if (s->dtype == QSIM_C128)
-            hipLaunchKernelGGL(k_xor_permute<double>, dim3(grid_for(N, kBlock * 4)), dim3(kBlock), 0, s->stream,
-                               static_cast<double *>(s->data), N, f, x_first, X - 1, f_first);
-        else
-            hipLaunchKernelGGL(k_xor_permute<float>, dim3(grid_for(N, kBlock * 4)), dim3(kBlock), 0, s->stream,
-                               static_cast<float *>(s->data), N, f, x_first, X - 1, f_first);
-        e = hipGetLastError();
-    }
-    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);  // the table is freed below
-    (void)hipFree(f);
-    QSIM_HIP(e);
+    const uint64_t xmask = (uint64_t(1) << x_qubits) - 1;
+    if (s->dtype == QSIM_C128)
+        hipLaunchKernelGGL(k_xor_permute<double>, dim3(grid_for(N, kBlock * 4)), dim3(kBlock), 0, s->stream,
+                           static_cast<double *>(s->data), N, lo, hi, x_first, xmask, h, f_first, G, minv);
+    else
+        hipLaunchKernelGGL(k_xor_permute<float>, dim3(grid_for(N, kBlock * 4)), dim3(kBlock), 0, s->stream,
+                           static_cast<float *>(s->data), N, lo, hi, x_first, xmask, h, f_first, G, minv);
+    QSIM_HIP(hipGetLastError());
     return QSIM_OK;
 }
 

@@ -10,6 +10,11 @@ kernels read), used by the CPU tests of the scheduler.
   halves split by a bit at the same thread position in both layouts; slots with the split bit
   squeezed out and one pad slot per 2^P) and checks that no two elements share a slot and every read
   returns the element the next layout expects.
+* `check_wave_barriers` follows, wavefront by wavefront, the control flow of the wave-split kernel
+  (its barriers sit in branches that are uniform per wavefront but differ between the two halves)
+  and checks that every wavefront passes the same number of barriers and that, with the k-th
+  barrier of each wavefront taken as one barrier instance, every LDS write of a round trip is
+  ordered before the reads that need it and every read before the writes that overwrite it.
 """
 import numpy as np
 
@@ -37,6 +42,9 @@ def load_tables(path):
     for o in O:  # factors of angle-defined diagonal ops, as the device fills them in
         if o['angles'] == 1:
             o['m'][0:4] = [1.0, 0.0, np.cos(o['theta'][0]), np.sin(o['theta'][0])]
+        elif o['angles'] == 3:
+            th = o['theta'][0] * np.ldexp(2 * np.pi, -int(o['theta'][1]))
+            o['m'][0:4] = [1.0, 0.0, np.cos(th), np.sin(th)]
         elif o['angles'] == 2:
             o['m'][0:4] = [np.cos(o['theta'][0]), np.sin(o['theta'][0]), np.cos(o['theta'][1]), np.sin(o['theta'][1])]
     return P, S, RD, O
@@ -217,3 +225,91 @@ def check_half_exchanges(P, S, m, le, c128):
             assert all(j >= 6 for j in js), 'a wave-split pass with a lane-level split'
             nwave += 1
     return nhalf, nwave
+
+
+def _wave_trace(ps, sts, w):
+    """Events of wavefront w of a wave-split pass, in program order: ('B',) for a barrier, ('W', k) /
+    ('R', k) for its LDS writes / reads of round trip k. Mirrors wave_out / wave_in: a wavefront is in
+    the second half of a round trip when its bit j (a thread position >= 6) is set."""
+    ev = []
+    k = [0]
+
+    def second(j):
+        return (w >> (j - 6)) & 1
+
+    def wave_out(j, pre):
+        if pre:
+            ev.append(('B',))
+        if second(j):
+            ev.extend([('B',), ('B',)])
+        ev.append(('W', k[0]))
+        ev.append(('B',))
+
+    def wave_in(j):
+        ev.append(('R', k[0]))
+        if not second(j):
+            ev.extend([('B',), ('B',)])
+        k[0] += 1
+
+    for i, st in enumerate(sts):
+        first, last = i == 0, i == len(sts) - 1
+        if not (first and ps['direct'] & 1):
+            if first:
+                wave_out(int(st['hj_in']), False)
+            wave_in(int(st['hj_in']))
+        if last:
+            break
+        wave_out(int(st['hj_out']), True)
+    if not ps['direct'] & 2:
+        wave_out(int(sts[-1]['hj_out']), True)
+        wave_in(int(sts[-1]['hj_out']))
+    return ev
+
+
+def check_wave_barriers(P, S, m, le):
+    """Returns the number of wave-split passes checked."""
+    lt = m - le
+    nw = 1 << (lt - 6)
+    checked = 0
+    for ps in P:
+        if (ps['direct'] & 12) != 12:
+            continue
+        sts = [S[i] for i in range(ps['sb'], ps['se'])]
+        traces = [_wave_trace(ps, sts, w) for w in range(nw)]
+        nb = [sum(1 for e in t if e[0] == 'B') for t in traces]
+        assert len(set(nb)) == 1, f'wavefronts pass different numbers of barriers: {nb}'
+        # (wave, barriers passed before the event) of every write and read of each round trip
+        W, R = {}, {}
+        for w, t in enumerate(traces):
+            nbar = 0
+            for e in t:
+                if e[0] == 'B':
+                    nbar += 1
+                else:
+                    (W if e[0] == 'W' else R).setdefault(e[1], []).append((w, nbar))
+
+        def before(a, b):  # a happens before b: same wavefront in program order, or a barrier between
+            return (a[0] == b[0] and a[1] <= b[1]) or a[1] < b[1]
+
+        nrt = len(W)
+        assert sorted(W) == sorted(R) == list(range(nrt))
+        js = []
+        if not ps['direct'] & 1:
+            js.append(int(sts[0]['hj_in']))
+        js += [int(st['hj_out']) for st in sts[:-1]]
+        if not ps['direct'] & 2:
+            js.append(int(sts[-1]['hj_out']))
+        assert len(js) == nrt
+        for k in range(nrt):
+            half = {w: (w >> (js[k] - 6)) & 1 for w in range(nw)}
+            for h in (0, 1):
+                ws = [e for e in W[k] if half[e[0]] == h]
+                rs = [e for e in R[k] if half[e[0]] == h]
+                assert all(before(a, b) for a in ws for b in rs), f'round trip {k}: a read before a write of its half'
+            r0 = [e for e in R[k] if half[e[0]] == 0]
+            w1 = [e for e in W[k] if half[e[0]] == 1]
+            assert all(before(a, b) for a in r0 for b in w1), f'round trip {k}: the second half writes before the first reads'
+            if k + 1 < nrt:
+                assert all(before(a, b) for a in R[k] for b in W[k + 1]), f'round trip {k + 1} writes before {k} is read'
+        checked += 1
+    return checked

@@ -79,7 +79,8 @@ def test_validation_rejects_before_device(L):
     assert L.qsim_norm(None, None) == _lib.EINVAL
     assert b"null" in L.qsim_last_error()
     for bad in [_g("H", 4), _g("X", 1, controls=0b10), _g("X", 0, controls=1 << 4),
-                _g("SWAP", 1, t2=1), _g("SWAP", 1, t2=9), _g("PHASE", 0, theta=float("nan"))]:
+                _g("SWAP", 1, t2=1), _g("SWAP", 1, t2=9), _g("PHASE", 0, theta=float("nan")), _g("RK", 0, t2=64),
+                _g("RKDG", 1, t2=-1)]:
         rc, _ = _plan(L, 4, [bad])
         assert rc == _lib.EINVAL, (bad.op, bad.target)
     g = _g("H", 0)
@@ -115,7 +116,8 @@ def test_circuit_parser_maps_keywords():
     g = c.gates
     assert (g[1].op, g[1].target, g[1].controls) == (_lib.OPS["X"], 1, 1)
     assert (g[2].op, g[2].target, g[2].controls) == (_lib.OPS["X"], 2, 3)
-    assert g[3].op == _lib.OPS["PHASE"] and g[3].theta == 2 * 3.141592653589793 / 16 and g[3].controls == 2
-    assert g[4].theta == -g[3].theta
+    # the phase shifts 2 pi / 2^k cross the ABI as the integer k; the library forms the angle
+    assert (g[3].op, g[3].target, g[3].target2, g[3].controls) == (_lib.OPS["RK"], 3, 4, 2)
+    assert (g[4].op, g[4].target, g[4].target2, g[4].controls) == (_lib.OPS["RKDG"], 3, 4, 2)
     assert (g[5].op, g[5].target, g[5].target2) == (_lib.OPS["SWAP"], 0, 4)
     assert g[6].theta == 1.5 and g[7].theta == 0.5 and list(g[8].u) == [1, 0, 0, 0, 0, 0, 1, 0]

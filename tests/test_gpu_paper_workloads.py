@@ -58,7 +58,9 @@ def shor_table():
 # ----------------------------------------------------------------------------------------------
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
 @pytest.mark.parametrize("n,xf,xq,ff,fq,y,G", [(9, 4, 5, 0, 4, 7, 13), (12, 0, 8, 8, 4, 7, 15),
-                                               (14, 3, 6, 9, 5, 5, 21), (16, 0, 10, 10, 6, 2, 61)])
+                                               (14, 3, 6, 9, 5, 5, 21), (16, 0, 10, 10, 6, 2, 61),
+                                               (20, 0, 1, 1, 19, 5, 524287), (24, 0, 13, 13, 11, 1234, 2039),
+                                               (24, 11, 13, 0, 11, 2, 1999)])
 def test_modexp_bit_exact(q, oracle_mod, dtype, n, xf, xq, ff, fq, y, G):
     psi = wl.gaussian_state(n, 100 + n)
     if dtype == "c64":

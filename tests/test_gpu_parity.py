@@ -355,17 +355,40 @@ STAGED_VARIANTS = [("c128", m, le) for m, le in ((10, 3), (11, 3), (12, 3), (10,
 
 @pytest.mark.parametrize("dtype,m,le", STAGED_VARIANTS)
 def test_staged_every_variant(q, oracle_mod, dtype, m, le):
+    """Each block shape on two circuit families; each run twice: on a state set to |0...0>, and from
+    zero on a state holding other values (the first pass then generates |0...0> in its loads)."""
     n = 16
+    junk = wl.gaussian_state(n, 77)
     for text in (wl.brickwork_circuit(n, 6, seed=29), wl.config0_circuit(n, 80, seed=5)):
         ref = oracle_mod.run_circuit(text)
         c = q.parse_circuit(text)
         s = q.State(c.n, dtype)
         p = q.Plan(c, dtype, method="staged", lds_qubits=m, lds_regs=le)
         assert p.info["lds_qubits"] == m and p.info["lds_regs"] == le
+        kind, var = p.launches()
+        print(f"staged m={m} le={le}: forms {''.join('FHW'[v] for v in var)}", flush=True)
         p.execute(s)
         compare_circuit(s.download().astype(np.complex128), ref, dtype, f"staged m={m} le={le}")
+        s.upload(junk)
+        p.execute_from_zero(s)
+        compare_circuit(s.download().astype(np.complex128), ref, dtype, f"staged m={m} le={le} from zero")
         p.close()
         s.close()
+
+
+@pytest.mark.parametrize("method", ["plain", "fused"])
+def test_execute_from_zero_unstaged(q, oracle_mod, method):
+    n = 12
+    text = wl.config0_circuit(n, 60, seed=2)
+    ref = oracle_mod.run_circuit(text)
+    s = q.State(n, "c128")
+    s.upload(wl.gaussian_state(n, 5))
+    p = q.Plan(q.parse_circuit(text), "c128", method=method)
+    p.execute_from_zero(s)
+    compare_circuit(s.download(), ref, "c128", f"{method} from zero")
+    ms, kind, fk = p.execute_timed(s, from_zero=True)
+    assert len(ms) == p.info["launches"]
+    compare_circuit(s.download(), ref, "c128", f"{method} timed from zero")
 
 
 @pytest.mark.parametrize("n,dtype,m,le,most", [(33, "c128", 12, 4, 14), (33, "c128", 11, 4, 19), (33, "c128", 10, 4, 24),
@@ -488,3 +511,73 @@ def test_batch_variants(q, oracle_mod, variant):
     b.run()
     for c, t in enumerate(texts):
         compare_circuit(b.download(c), oracle_mod.run_circuit(t), "c128", f"{variant} circuit {c}")
+
+
+# ----------------------------------------------------------------------------------------------
+# The autotuner's choice, and the library-owned allocation
+# ----------------------------------------------------------------------------------------------
+@pytest.mark.parametrize("dtype,n", [("c128", 20), ("c64", 21)])
+def test_tuned_plan_matches_oracle(q, oracle_mod, dtype, n, tmp_path, monkeypatch):
+    """qsim_plan_tune times every candidate (plain, fused k = 2..5, the staged block shapes) on a
+    scratch state; the plan it picks, built again from the returned options, reproduces the oracle,
+    and the JSON cache returns the same choice on a second call."""
+    from paper_quant_ph_0608239_amd import tuning
+    monkeypatch.setenv("QSIM_TUNE_CACHE", str(tmp_path / "tune.json"))
+    text = wl.brickwork_circuit(n, 8, seed=21)
+    c = q.parse_circuit(text)
+    s = q.State(n, dtype)
+    t = tuning.tune(c, s, reps=1, include_plain=True, use_cache=True)
+    ran = [x for x in t["tried"] if x["ms"] > 0]
+    print(f"tune {dtype} n={n}: {t['method']} k={t['fuse_k']} m={t['lds_qubits']} r={t['lds_regs']} "
+          f"{t['ms']:.3f} ms; {len(ran)} of {len(t['tried'])} candidates timed", flush=True)
+    assert t["ms"] > 0 and len(ran) >= 1 and t["method"] in ("plain", "fused", "staged")
+    assert t["ms"] <= min(x["ms"] for x in ran) + 1e-9
+    again = tuning.tune(c, s, reps=1, include_plain=True, use_cache=True)
+    assert again["cached"] and {k: again[k] for k in ("method", "fuse_k", "lds_qubits", "lds_regs")} == \
+        {k: t[k] for k in ("method", "fuse_k", "lds_qubits", "lds_regs")}
+    p = q.Plan(c, dtype, method=t["method"], fuse_k=t["fuse_k"] or 5, lds_qubits=t["lds_qubits"], lds_regs=t["lds_regs"])
+    s.set_basis(0)
+    p.execute(s)
+    got = s.download().astype(np.complex128)
+    ref = oracle_mod.run_circuit(text)
+    if dtype == "c128":
+        assert np.max(np.abs(got - ref)) <= TOL128
+    else:
+        assert oracle_mod.infidelity(got, ref) <= TOL64_FID
+    p.close()
+    s.close()
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_library_owned_state(q, oracle_mod, dtype):
+    """qsim_alloc: the library allocates the state and sets it to |0...0>; gates and reductions run on
+    it like on a wrapped buffer; qsim_free releases it. A state larger than the free device memory is
+    refused with ENOMEM before anything is allocated."""
+    import ctypes
+    from paper_quant_ph_0608239_amd import _lib
+    L = q.lib()
+    n = 14
+    code = q.dtype_code(dtype)
+    h = ctypes.c_void_p()
+    assert L.qsim_alloc(n, code, None, ctypes.byref(h)) == _lib.OK
+    try:
+        assert L.qsim_num_qubits(h) == n and L.qsim_get_dtype(h) == code and L.qsim_data(h)
+        cd = np.complex128 if dtype == "c128" else np.complex64
+        out = np.empty(2 ** n, dtype=cd)
+        assert L.qsim_download(h, out.ctypes.data_as(ctypes.c_void_p), out.nbytes) == _lib.OK
+        assert out[0] == 1 and np.count_nonzero(out) == 1
+        H = np.array([[1, 1], [1, -1]]) / np.sqrt(2)
+        flat = (ctypes.c_double * 8)(*np.asarray(H, np.complex128).reshape(-1).view(np.float64).tolist())
+        for t in range(n):
+            assert L.qsim_apply_1q(h, t, flat) == _lib.OK
+        nrm = ctypes.c_double()
+        assert L.qsim_norm(h, ctypes.byref(nrm)) == _lib.OK
+        assert abs(nrm.value - 1.0) <= (1e-13 if dtype == "c128" else 1e-6)
+        assert L.qsim_download(h, out.ctypes.data_as(ctypes.c_void_p), out.nbytes) == _lib.OK
+        ref = oracle_mod.run_circuit(wl.circuit_text(n, [f"H {t}" for t in range(n)]))
+        check(out, ref, dtype, "H on every qubit of an owned state")
+    finally:
+        assert L.qsim_free(h) == _lib.OK
+    big = ctypes.c_void_p()
+    assert L.qsim_alloc(40, code, None, ctypes.byref(big)) == _lib.ENOMEM
+    assert not big.value

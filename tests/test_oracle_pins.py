@@ -388,3 +388,81 @@ def test_probs_and_marginals_basis(oracle_mod):
     assert list(q) == [float((x >> i) & 1) for i in range(n)]
     p = oracle_mod.probs(psi)
     assert p[x] == 1.0 and p.sum() == 1.0
+
+
+# ----------------------------------------------------------------------------------------------
+# The two error-metric and Fourier helpers used as references by the GPU tests
+# ----------------------------------------------------------------------------------------------
+def _orthogonal_to(psi, seed):
+    """A normalised state orthogonal to psi (Gram-Schmidt of a seeded Gaussian vector)."""
+    v = wl.gaussian_state(int(round(math.log2(psi.size))), seed).astype(np.complex128)
+    u = psi / np.linalg.norm(psi)
+    v = v - np.vdot(u, v) * u
+    return v / np.linalg.norm(v)
+
+
+def test_infidelity_closed_forms(oracle_mod):
+    """1 - F with F = |<ref|psi>|^2 / (<ref|ref><psi|psi>): 0 for a global phase and any scaling,
+    1 for orthogonal states, sin^2 t for cos t ref + sin t e^{ia} ref_perp (a missing conjugate, a
+    missing norm factor or a swapped argument order changes at least one of these)."""
+    n = 10
+    ref = wl.gaussian_state(n, 41).astype(np.complex128)
+    perp = _orthogonal_to(ref, 42)
+    for phase in (0.0, 0.3, 2.1, math.pi):
+        assert abs(oracle_mod.infidelity(np.exp(1j * phase) * ref, ref)) < 1e-14
+    assert abs(oracle_mod.infidelity(3.0 * ref, ref)) < 1e-14
+    assert abs(oracle_mod.infidelity(ref, 0.25j * ref)) < 1e-14
+    assert abs(oracle_mod.infidelity(perp, ref) - 1.0) < 1e-14
+    for t in (1e-3, 0.2, 0.7, 1.3):
+        for a in (0.0, 1.1):
+            psi = math.cos(t) * ref + math.sin(t) * np.exp(1j * a) * perp
+            want = math.sin(t) ** 2
+            assert abs(oracle_mod.infidelity(psi, ref) - want) < 1e-13 * max(1.0, want / 1e-6)
+            # symmetric in its two arguments
+            assert abs(oracle_mod.infidelity(ref, psi) - want) < 1e-13 * max(1.0, want / 1e-6)
+
+
+def test_max_abs_diff_is_complex_modulus(oracle_mod):
+    a = np.array([1 + 1j, 0.5, -2j])
+    b = np.array([1 + 1j, 0.5 + 0.3j, 2j])
+    assert oracle_mod.max_abs_diff(a, b) == 4.0
+    assert oracle_mod.max_abs_diff(a, a) == 0.0
+    assert abs(oracle_mod.max_abs_diff(np.array([3 + 4j]), np.array([0j])) - 5.0) < 1e-15
+
+
+@pytest.mark.parametrize("n", [1, 4, 9, 12])
+def test_qft_sample_equals_gate_level_qft(oracle_mod, n):
+    """The sampled Fourier outputs (one O(2^n) sum per k) equal, at every k, the state that the
+    gate-level QFT circuit (Hadamards, controlled phase shifts 2 pi / 2^k, bit-reversal swaps)
+    produces in the oracle, whose circuit is pinned to the DFT and to numpy's FFT above."""
+    psi = rand_state(n, 70 + n)
+    full = oracle_mod.run_circuit(wl.qft_circuit(n), psi0=psi)
+    ks = list(range(2 ** n))
+    got = oracle_mod.qft_sample(psi, ks)
+    assert np.max(np.abs(got - full)) < 1e-13
+
+
+def test_qft_sample_equals_fft_library(oracle_mod):
+    """numpy's inverse FFT with orthonormal scaling is the same transform (sign +2 pi i x k / N)."""
+    n = 16
+    psi = rand_state(n, 12)
+    rng = np.random.default_rng(16)
+    ks = [0, 1, 2, 2 ** (n - 1), 2 ** n - 1] + [int(k) for k in rng.integers(0, 2 ** n, size=27)]
+    got = oracle_mod.qft_sample(psi, ks)
+    want = np.fft.ifft(psi, norm="ortho")[ks]
+    assert np.max(np.abs(got - want)) < 1e-13
+
+
+def test_qft_sample_closed_forms(oracle_mod):
+    """Basis state |x>: out_k = 2^{-n/2} e^{2 pi i x k / 2^n}; uniform state: out_k = [k = 0]."""
+    n = 11
+    N = 2 ** n
+    for x in (0, 1, 5, N - 1, 1234):
+        psi = np.zeros(N, dtype=np.complex128)
+        psi[x] = 1.0
+        ks = [0, 1, 3, 700, N - 1]
+        want = np.array([cmath.exp(2j * math.pi * ((x * k) % N) / N) for k in ks]) / math.sqrt(N)
+        assert np.max(np.abs(oracle_mod.qft_sample(psi, ks) - want)) < 1e-14
+    u = np.full(N, 1.0 / math.sqrt(N), dtype=np.complex128)
+    got = oracle_mod.qft_sample(u, [0, 1, 2, N // 2, N - 1])
+    assert abs(got[0] - 1.0) < 1e-13 and np.max(np.abs(got[1:])) < 1e-13

@@ -94,6 +94,8 @@ def test_schedule_reproduces_oracle(dumper, tmp_path, oracle_mod, case, c128, m,
     got = sm.run_schedule(psi0, n, m, le, P, S, RD, O)
     assert np.max(np.abs(got - ref)) < 1e-12
     sm.check_half_exchanges(P, S, m, le, c128)
+    if m - le >= 7:
+        sm.check_wave_barriers(P, S, m, le)
 
 
 def test_brickwork_passes_use_wave_splits(dumper, tmp_path):
@@ -103,3 +105,41 @@ def test_brickwork_passes_use_wave_splits(dumper, tmp_path):
     P, S, RD, O = tables(dumper, tmp_path, text, 16, True, 12, 4)
     nhalf, nwave = sm.check_half_exchanges(P, S, 12, 4, True)
     assert nhalf == len(P) and nwave == len(P)
+    assert sm.check_wave_barriers(P, S, 12, 4) == len(P)
+
+
+def test_wave_barrier_model_catches_a_missing_barrier(dumper, tmp_path, monkeypatch):
+    """The barrier check fails when one half of a round trip skips a barrier (planted in the model)."""
+    text = wl.brickwork_circuit(16, 8, seed=21)
+    P, S, RD, O = tables(dumper, tmp_path, text, 16, True, 12, 4)
+    orig = sm._wave_trace
+
+    def drop_one(ps, sts, w):
+        ev = orig(ps, sts, w)
+        if w == 0:
+            ev.remove(('B',))
+        return ev
+
+    monkeypatch.setattr(sm, "_wave_trace", drop_one)
+    with pytest.raises(AssertionError):
+        sm.check_wave_barriers(P, S, 12, 4)
+
+
+def test_wave_barrier_model_catches_an_early_write(dumper, tmp_path, monkeypatch):
+    """The ordering check fails when the second half writes before its two waiting barriers (the
+    barrier count stays equal; planted in the model)."""
+    text = wl.brickwork_circuit(16, 8, seed=21)
+    P, S, RD, O = tables(dumper, tmp_path, text, 16, True, 12, 4)
+    orig = sm._wave_trace
+
+    def early(ps, sts, w):
+        ev = orig(ps, sts, w)
+        for i in range(len(ev) - 2):
+            if ev[i] == ('B',) and ev[i + 1] == ('B',) and ev[i + 2][0] == 'W':
+                ev[i], ev[i + 2] = ev[i + 2], ev[i]
+                break
+        return ev
+
+    monkeypatch.setattr(sm, "_wave_trace", early)
+    with pytest.raises(AssertionError):
+        sm.check_wave_barriers(P, S, 12, 4)
