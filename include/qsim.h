@@ -156,6 +156,20 @@ int qsim_marginals(qsim_state *s, double *out);
  * EINVAL if the norm is 0. Synchronises. */
 int qsim_renormalize(qsim_state *s, double *norm_before);
 
+/* Allocation-free form of qsim_renormalize, for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc. It takes the amplitudes of a
+ * state as a raw device buffer (dev_amps: 2^n amplitudes of the given dtype, 16-byte aligned; 1 <= n
+ * <= QSIM_MAX_QUBITS) and rescales them to unit norm in place with the kernels and reduction grid of
+ * qsim_renormalize (same results, bit for bit). The FP64 norm before the rescale is written to
+ * dev_norm_before (a device pointer to one double, may be NULL). A state of norm 0 is left unchanged
+ * (its norm, 0, is still reported). The norm partials (at most 4096) and the norm live in a static
+ * device array of 32.8 KB, one per device, held until the process ends: the call allocates nothing,
+ * never synchronises and is asynchronous on hip_stream (NULL: the null stream). Calls that overlap on
+ * one device share that array and race: serialise them (one stream, or events). Nothing has to be
+ * cleared between calls. EINVAL on a NULL or misaligned buffer, n or dtype out of range; EDEVICE if a
+ * launch fails. */
+int qsim_renormalize_noalloc(void *dev_amps, int n, int dtype, void *hip_stream, double *dev_norm_before);
+
 /* Draw `shots` basis states with probability |a_x|^2 (Sec. V: sampling of the final state).
  * uniforms: host array of `shots` doubles in [0, 1) supplied by the caller; out: host array of
  * `shots` indices. Inverse-CDF sampling over the FP64 cumulative probabilities. Synchronises. */

@@ -89,6 +89,7 @@ SIGNATURES = {
     "qsim_probs": (_i32, [_vp, _vp, _i32]),
     "qsim_marginals": (_i32, [_vp, _dp]),
     "qsim_renormalize": (_i32, [_vp, _dp]),
+    "qsim_renormalize_noalloc": (_i32, [_vp, _i32, _i32, _vp, _vp]),
     "qsim_sample": (_i32, [_vp, _i64, _dp, ctypes.POINTER(_u64)]),
     "qsim_plan_create": (_i32, [_i32, _i32, ctypes.POINTER(Gate), _i64, ctypes.POINTER(PlanOpts), ctypes.POINTER(_vp)]),
     "qsim_plan_get_info": (_i32, [_vp, ctypes.POINTER(PlanInfo)]),

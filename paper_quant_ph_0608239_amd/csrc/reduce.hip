@@ -3,6 +3,7 @@
 //   <Q_q> = sum_k |a_k|^2 bit_q(k) (Eq. Shor7), renormalisation, and inverse-CDF sampling.
 // Every reduction uses a grid fixed by the state size and fixed-order tree sums, so results are
 // deterministic run to run.
+#include <mutex>
 #include <type_traits>
 
 #include "qsim_internal.h"
@@ -417,4 +418,67 @@ int run_sample(qsim_state *s, int64_t shots, const double *uniforms, uint64_t *o
     return QSIM_OK;
 }
 
+// ---- allocation-free renormalisation ---------------------------------------------------------------
+// For callers that cannot allocate device memory, the norm partials (at most one per block of the
+// fixed reduction grid, 4096) and the norm live in a file-scope device array instead of the state's
+// scratch buffer: one copy per device, held until the process ends. In host code the array's name is
+// only a stand-in; its device address is taken once per device with hipGetSymbolAddress and used
+// everywhere host code needs the array.
+constexpr int kNoAllocPartials = 4096;
+constexpr int kNoAllocDoubles = 8 + kNoAllocPartials;
+static __device__ __align__(256) double noalloc_scratch[kNoAllocDoubles];
+
+constexpr int kNoAllocMaxDevices = 64;
+static std::mutex g_noalloc_mu;
+static double *g_noalloc_ptr[kNoAllocMaxDevices] = {};
+
+// the device address of this device's copy of the array (taken on the first call on the device, with
+// that device current)
+static int noalloc_scratch_ptr(double **out)
+{
+    int dev = 0;
+    QSIM_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kNoAllocMaxDevices) return set_error(QSIM_EUNSUPPORTED, "renormalize_noalloc: device index too large");
+    std::lock_guard<std::mutex> lock(g_noalloc_mu);
+    if (!g_noalloc_ptr[dev]) {
+        void *p = nullptr;
+        QSIM_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(noalloc_scratch)));
+        if (!p) return set_error(QSIM_EDEVICE, "renormalize_noalloc: no device address for the scratch array");
+        g_noalloc_ptr[dev] = static_cast<double *>(p);
+    }
+    *out = g_noalloc_ptr[dev];
+    return QSIM_OK;
+}
+
 }  // namespace qsim
+
+extern "C" int qsim_renormalize_noalloc(void *dev_amps, int n, int dtype, void *hip_stream, double *dev_norm_before)
+{
+    using namespace qsim;
+    if (!dev_amps) return set_error(QSIM_EINVAL, "renormalize_noalloc: dev_amps is NULL");
+    if (reinterpret_cast<uintptr_t>(dev_amps) % 16) return set_error(QSIM_EINVAL, "renormalize_noalloc: dev_amps must be 16-byte aligned");
+    if (n < 1 || n > QSIM_MAX_QUBITS) return set_error(QSIM_EINVAL, "renormalize_noalloc: n out of range (1..QSIM_MAX_QUBITS)");
+    if (dtype != QSIM_C64 && dtype != QSIM_C128) return set_error(QSIM_EINVAL, "renormalize_noalloc: unknown dtype");
+    const uint64_t N = dim(n);
+    const unsigned g = reduce_grid(dtype == QSIM_C128 ? N : N / 2 + 1);
+    if (g > unsigned(kNoAllocPartials)) return set_error(QSIM_EINVAL, "renormalize_noalloc: more partial sums than the scratch holds");
+    double *scr = nullptr;
+    if (int rc = noalloc_scratch_ptr(&scr)) return rc;
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    double *partial = scr + 8;
+    // the same kernels and grid as qsim_renormalize: the partials are overwritten, nothing needs clearing
+    if (dtype == QSIM_C128)
+        hipLaunchKernelGGL(k_norm_partial<double>, dim3(g), dim3(kBlock), 0, st, static_cast<const double *>(dev_amps), N, partial);
+    else
+        hipLaunchKernelGGL(k_norm_partial<float>, dim3(g), dim3(kBlock), 0, st, static_cast<const float *>(dev_amps), N, partial);
+    QSIM_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(kBlock), 0, st, partial, int(g), 1, 1, scr);
+    QSIM_HIP(hipGetLastError());
+    const unsigned gs = reduce_grid(N);
+    if (dtype == QSIM_C128)
+        hipLaunchKernelGGL(k_scale<double>, dim3(gs), dim3(kBlock), 0, st, static_cast<double *>(dev_amps), N, scr, 2, dev_norm_before);
+    else
+        hipLaunchKernelGGL(k_scale<float>, dim3(gs), dim3(kBlock), 0, st, static_cast<float *>(dev_amps), N, scr, 2, dev_norm_before);
+    QSIM_HIP(hipGetLastError());
+    return QSIM_OK;
+}
