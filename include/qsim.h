@@ -321,17 +321,34 @@ typedef struct qsim_batch_stats {
 /* Build a batch of `count` circuits for one dtype: circuit c has nqubits[c] qubits (1..26) and the
  * gates gates[offsets[c] .. offsets[c+1]-1] (offsets has count + 1 entries, offsets[0] = 0); every
  * circuit starts from |0...0>. Each circuit is scheduled into LDS-staged passes (opts: lds_qubits,
- * lds_regs as for QSIM_PLAN_STAGED; use_graph records the launch in a HIP graph on the first run,
- * which needs a non-NULL stream; opts may be NULL). The gate tables and the state pool are placed in
- * device memory owned by the batch. EINVAL on malformed input, ENOMEM if the pool does not fit. */
+ * lds_regs as for QSIM_PLAN_STAGED; use_graph records the run's launch sequence in a HIP graph on the
+ * first run, which needs a non-NULL stream; opts may be NULL). A circuit whose state holds at least 8
+ * LDS blocks is split: each of its passes runs as chunks of 4 blocks that any workgroup may take, pass
+ * p in launch step p; smaller circuits run whole on one workgroup in step 0. The gate tables, the
+ * work lists and the state pool are placed in device memory owned by the batch. EINVAL on malformed
+ * input, ENOMEM if the pool does not fit. */
 int qsim_batch_create(int count, const int *nqubits, const int64_t *offsets, const qsim_gate *gates, int dtype,
                       const qsim_plan_opts *opts, void *stream, qsim_batch **out);
-/* Run every circuit of the batch from |0...0> in one persistent kernel launch (workgroups walk the
- * circuits largest first in a fixed cyclic order). stats may be NULL. Per-circuit device timestamps
- * (start -> finish) are kept for qsim_batch_latencies. Synchronises. */
+/* Run every circuit of the batch from |0...0>: one short launch that clears the stamps, then per
+ * launch step one persistent kernel per kernel form (wave-split, half-buffer or full-buffer LDS
+ * passes), workgroups walking the step's items in a fixed cyclic order (whole circuits first,
+ * largest first). stats may be NULL. Per-circuit device timestamps (first start of its first pass ->
+ * last end of its last pass) are kept for qsim_batch_latencies. Synchronises. */
 int qsim_batch_run(qsim_batch *b, qsim_batch_stats *stats);
 /* Per-circuit latencies of the last run in microseconds (host array of count doubles). */
 int qsim_batch_latencies(qsim_batch *b, double *out_us);
+
+typedef struct qsim_batch_info {
+    int64_t circuits;       /* circuits in the batch */
+    int64_t gates;          /* gates over all circuits */
+    int64_t split_circuits; /* circuits whose passes are split over workgroups */
+    int64_t steps;          /* launch steps (the most passes of a split circuit, at least 1) */
+    int64_t launches;       /* kernel launches per run */
+    int32_t lds_qubits;     /* resident qubits per LDS block */
+    int32_t lds_regs;       /* log2 amplitudes per thread */
+} qsim_batch_info;
+/* Shape of a batch's schedule (host only). */
+int qsim_batch_get_info(const qsim_batch *b, qsim_batch_info *info);
 /* Copy circuit c's final state (2^nqubits[c] amplitudes) to host memory. */
 int qsim_batch_download(qsim_batch *b, int c, void *host, size_t bytes);
 int qsim_batch_free(qsim_batch *b);

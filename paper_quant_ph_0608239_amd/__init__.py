@@ -270,6 +270,9 @@ class Batch:
             check(lib().qsim_batch_create(self.count, nq, of, garr, self.dtype, ctypes.byref(opts),
                                           _stream_ptr(torch.device(device)), ctypes.byref(h)))
         self.handle = h
+        info = _lib.BatchInfo()
+        check(lib().qsim_batch_get_info(h, ctypes.byref(info)))
+        self.info = {f: getattr(info, f) for f, _ in _lib.BatchInfo._fields_}
 
     def run(self) -> dict:
         st = _lib.BatchStats()

@@ -57,6 +57,12 @@ class BatchStats(ctypes.Structure):
     _fields_ = [("launch_ms", ctypes.c_double), ("circuits", ctypes.c_int64), ("gates", ctypes.c_int64)]
 
 
+class BatchInfo(ctypes.Structure):
+    _fields_ = [("circuits", ctypes.c_int64), ("gates", ctypes.c_int64), ("split_circuits", ctypes.c_int64),
+                ("steps", ctypes.c_int64), ("launches", ctypes.c_int64), ("lds_qubits", ctypes.c_int32),
+                ("lds_regs", ctypes.c_int32)]
+
+
 assert ctypes.sizeof(Gate) == 96
 
 _lib = None
@@ -105,6 +111,7 @@ SIGNATURES = {
                                  ctypes.POINTER(PlanOpts), _vp, ctypes.POINTER(_vp)]),
     "qsim_batch_run": (_i32, [_vp, ctypes.POINTER(BatchStats)]),
     "qsim_batch_latencies": (_i32, [_vp, _dp]),
+    "qsim_batch_get_info": (_i32, [_vp, ctypes.POINTER(BatchInfo)]),
     "qsim_batch_download": (_i32, [_vp, _i32, _vp, _sz]),
     "qsim_batch_free": (_i32, [_vp]),
 }

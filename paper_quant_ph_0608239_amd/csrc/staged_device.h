@@ -725,22 +725,29 @@ __device__ __forceinline__ void run_block_half(T *__restrict__ a, const SPass &p
 #pragma unroll
         for (int j = 0; j < LOG_T; ++j)
             if ((t >> j) & 1) gt |= uint64_t(1) << st.ptb[j];
-        const C *ag = reinterpret_cast<const C *>(a) + gt;
+        if (init_zero) {  // |0...0>: only element 0 of thread 0 of block 0 is 1
 #pragma unroll
-        for (int r = 0; r < E; ++r) {
-            uint64_t v = 0;
+            for (int r = 0; r < E; ++r) x[r] = C{(gt == 0 && r == 0) ? T(1) : T(0), T(0)};
+        } else {
+            const C *ag = reinterpret_cast<const C *>(a) + gt;
 #pragma unroll
-            for (int j = 0; j < LOG_E; ++j)
-                if ((r >> j) & 1) v |= uint64_t(1) << st.prb[j];
-            x[r] = init_zero ? C{(gt | v) == 0 ? T(1) : T(0), T(0)} : ld_nt(ag + v);
+            for (int r = 0; r < E; ++r) {
+                uint64_t v = 0;
+#pragma unroll
+                for (int j = 0; j < LOG_E; ++j)
+                    if ((r >> j) & 1) v |= uint64_t(1) << st.prb[j];
+                x[r] = ld_nt(ag + v);
+            }
         }
     } else {
         const uint64_t g0 = base | lane_part<LOG_T>(pass, t);
-        const C *ag = reinterpret_cast<const C *>(a) + g0;
+        if (init_zero) {
 #pragma unroll
-        for (int k = 0; k < E; ++k) {
-            const uint64_t ek = elem_part<LOG_E, LOG_T>(pass, k);
-            x[k] = init_zero ? C{(g0 | ek) == 0 ? T(1) : T(0), T(0)} : ld_nt(ag + ek);
+            for (int k = 0; k < E; ++k) x[k] = C{(g0 == 0 && k == 0) ? T(1) : T(0), T(0)};
+        } else {
+            const C *ag = reinterpret_cast<const C *>(a) + g0;
+#pragma unroll
+            for (int k = 0; k < E; ++k) x[k] = ld_nt(ag + elem_part<LOG_E, LOG_T>(pass, k));
         }
         int so[E];
         half_slots<T, LOG_E>(st.rb, st.hb_in, so);
@@ -861,24 +868,31 @@ __device__ __forceinline__ void run_block_wave(T *__restrict__ a, const SPass &p
 #pragma unroll
             for (int j = 0; j < LOG_T; ++j)
                 if ((t >> j) & 1) gt |= uint64_t(1) << st.ptb[j];
-            const C *ag = reinterpret_cast<const C *>(a) + gt;
+            if (init_zero) {  // |0...0>: only element 0 of thread 0 of block 0 is 1
 #pragma unroll
-            for (int r = 0; r < E; ++r) {
-                uint64_t v = 0;
+                for (int r = 0; r < E; ++r) x[r] = C{(gt == 0 && r == 0) ? T(1) : T(0), T(0)};
+            } else {
+                const C *ag = reinterpret_cast<const C *>(a) + gt;
 #pragma unroll
-                for (int j = 0; j < LOG_E; ++j)
-                    if ((r >> j) & 1) v |= uint64_t(1) << st.prb[j];
-                x[r] = init_zero ? C{(gt | v) == 0 ? T(1) : T(0), T(0)} : ld_nt(ag + v);
+                for (int r = 0; r < E; ++r) {
+                    uint64_t v = 0;
+#pragma unroll
+                    for (int j = 0; j < LOG_E; ++j)
+                        if ((r >> j) & 1) v |= uint64_t(1) << st.prb[j];
+                    x[r] = ld_nt(ag + v);
+                }
             }
         } else {
             if (first) {
                 uint64_t g0 = base | lane_part<LOG_T>(pass, t);
                 asm volatile("" : "+v"(g0));  // not kept alive until the store
-                const C *ag = reinterpret_cast<const C *>(a) + g0;
+                if (init_zero) {
 #pragma unroll
-                for (int k = 0; k < E; ++k) {
-                    const uint64_t ek = elem_part<LOG_E, LOG_T>(pass, k);
-                    x[k] = init_zero ? C{(g0 | ek) == 0 ? T(1) : T(0), T(0)} : ld_nt(ag + ek);
+                    for (int k = 0; k < E; ++k) x[k] = C{(g0 == 0 && k == 0) ? T(1) : T(0), T(0)};
+                } else {
+                    const C *ag = reinterpret_cast<const C *>(a) + g0;
+#pragma unroll
+                    for (int k = 0; k < E; ++k) x[k] = ld_nt(ag + elem_part<LOG_E, LOG_T>(pass, k));
                 }
                 wave_out<T, E>(x, lds, slot<T>(int(squeeze(uint32_t(t), st.hb_in))), lso, st.hj_in, false);
             }

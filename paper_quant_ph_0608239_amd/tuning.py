@@ -80,3 +80,40 @@ def tune(circuit, scratch, reps: int = 1, include_plain: bool = False, use_cache
     r = dict(r)
     r["cached"] = False
     return r
+
+
+# LDS block shapes (resident qubits, log2 amplitudes per thread) that a batch can use, per dtype
+BATCH_SHAPES = {1: [(12, 4), (11, 4), (11, 3)], 0: [(12, 4), (11, 4), (13, 5)]}
+
+
+def tune_batch(circuits, dtype, reps: int = 2, use_cache: bool = False) -> dict:
+    """The fastest LDS block shape for a batch of circuits: each candidate batch is built, run once
+    (warm-up) and timed over `reps` runs (HIP events around each run) on the current stream. Returns
+    {"lds_qubits", "lds_regs", "ms", "tried": [...]}; cached by the circuits' gate lists if use_cache."""
+    import numpy as np
+
+    from . import Batch, dtype_code, parse_circuit
+    cs = [parse_circuit(c) if isinstance(c, str) else c for c in circuits]
+    code = dtype_code(dtype)
+    h = hashlib.sha256()
+    for c in cs:
+        h.update(bytes(f"{c.n}:{circuit_key(c, code)};", "ascii"))
+    key = f"batch-d{code}-{h.hexdigest()[:16]}"
+    db = _load() if use_cache else {}
+    if use_cache and key in db:
+        return dict(db[key], cached=True)
+    tried = []
+    for m, r in BATCH_SHAPES[code]:
+        b = Batch(cs, code, lds_qubits=m, lds_regs=r)
+        try:
+            b.run()
+            ms = float(np.mean([b.run()["launch_ms"] for _ in range(reps)]))
+        finally:
+            b.close()
+        tried.append({"lds_qubits": m, "lds_regs": r, "ms": ms})
+    best = min(tried, key=lambda t: t["ms"])
+    out = {"lds_qubits": best["lds_qubits"], "lds_regs": best["lds_regs"], "ms": best["ms"], "tried": tried}
+    if use_cache:
+        db[key] = out
+        _store(db)
+    return dict(out, cached=False)

@@ -504,13 +504,42 @@ def test_batch_graph_replay(q, oracle_mod):
                 compare_circuit(b.download(c), refs[c], "c128", f"replay {rep} circuit {c}")
 
 
-@pytest.mark.parametrize("variant", [(11, 3), (11, 4)])
-def test_batch_variants(q, oracle_mod, variant):
+@pytest.mark.parametrize("dtype,variant", [("c128", (11, 3)), ("c128", (11, 4)), ("c128", (12, 4)), ("c64", (11, 4)),
+                                           ("c64", (12, 4)), ("c64", (13, 5))])
+def test_batch_variants(q, oracle_mod, dtype, variant):
+    """Every block shape a batch can use, on circuits from below one block to 2^5 blocks: the larger
+    ones are split over workgroups (pass p of each in launch step p, in the wave-split, half-buffer or
+    full-buffer kernel that the pass allows), the smaller ones run whole."""
     texts = wl.batch_circuits(count=10, nmin=9, nmax=13, depth=40, seed=77)
-    b = q.Batch(texts, "c128", lds_qubits=variant[0], lds_regs=variant[1])
-    b.run()
-    for c, t in enumerate(texts):
-        compare_circuit(b.download(c), oracle_mod.run_circuit(t), "c128", f"{variant} circuit {c}")
+    texts += wl.batch_circuits(count=6, nmin=variant[0] + 3, nmax=variant[0] + 5, depth=60, seed=78)
+    b = q.Batch(texts, dtype, lds_qubits=variant[0], lds_regs=variant[1])
+    assert b.info["split_circuits"] >= 6 and b.info["lds_qubits"] == variant[0]
+    for rep in range(2):
+        b.run()
+        for c, t in enumerate(texts):
+            compare_circuit(b.download(c).astype(np.complex128), oracle_mod.run_circuit(t), dtype, f"{variant} circuit {c} rep {rep}")
+    lat = b.latencies_us()
+    assert np.all(lat > 0) and np.all(np.isfinite(lat))
+    b.close()
+
+
+def test_batch_tuned_shape_matches_oracle(q, oracle_mod):
+    """The batch autotuner builds and times every block shape; the batch built with its choice runs
+    through a HIP graph on a stream of its own and reproduces the oracle on every circuit."""
+    import torch
+    from paper_quant_ph_0608239_amd import tuning
+    texts = wl.batch_circuits(count=48, nmin=10, nmax=18, depth=50, seed=43)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        t = tuning.tune_batch(texts, "c128", reps=1)
+        print(f"batch tune: m={t['lds_qubits']} r={t['lds_regs']} {t['ms']:.3f} ms; tried {t['tried']}", flush=True)
+        assert len(t["tried"]) == 3 and t["ms"] == min(x["ms"] for x in t["tried"])
+        b = q.Batch(texts, "c128", lds_qubits=t["lds_qubits"], lds_regs=t["lds_regs"], use_graph=True)
+        for rep in range(2):
+            b.run()
+            for c, text in enumerate(texts):
+                compare_circuit(b.download(c), oracle_mod.run_circuit(text), "c128", f"tuned circuit {c} rep {rep}")
+        b.close()
 
 
 # ----------------------------------------------------------------------------------------------
