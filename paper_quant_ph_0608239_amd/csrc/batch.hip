@@ -50,16 +50,17 @@ enum Form { kFull = 0, kHalf = 1, kWave = 2 };
 // the workgroup may start another block
 template <typename T, int LOG_E, int LOG_T, int FORM>
 __device__ __forceinline__ void item_block(T *__restrict__ a, const SPass &pass, uint64_t b, cptr<SStage> stages,
-                                           cptr<SRound> rounds, cptr<SOp> ops, typename Vec<T>::C *lds, bool init)
+                                           cptr<SRound> rounds, cptr<SOp> ops, cptr<SBlk> blks, typename Vec<T>::C *lds,
+                                           bool init)
 {
     if constexpr (FORM == kWave) {
-        run_block_wave<T, LOG_E, LOG_T>(a, pass, b, stages, rounds, ops, lds, init);
+        run_block_wave<T, LOG_E, LOG_T>(a, pass, b, stages, rounds, ops, blks, lds, init);
         __syncthreads();
     } else if constexpr (FORM == kHalf) {
-        run_block_half<T, LOG_E, LOG_T>(a, pass, b, stages, rounds, ops, lds, init);
+        run_block_half<T, LOG_E, LOG_T>(a, pass, b, stages, rounds, ops, blks, lds, init);
         __syncthreads();
     } else {
-        run_block<T, LOG_E, LOG_T>(a, pass, b, stages, rounds, ops, lds, init);  // ends with a barrier
+        run_block<T, LOG_E, LOG_T>(a, pass, b, stages, rounds, ops, blks, lds, init);  // ends with a barrier
     }
 }
 
@@ -68,7 +69,8 @@ __global__ __launch_bounds__(1 << LOG_T, MINW) void k_batch(T *__restrict__ pool
                                                             const BatchItem *__restrict__ items, int nitems,
                                                             const SPass *__restrict__ passes, const SStage *__restrict__ stages,
                                                             const SRound *__restrict__ rounds, const SOp *__restrict__ ops,
-                                                            uint64_t *__restrict__ t_claim, uint64_t *__restrict__ t_done)
+                                                            const SBlk *__restrict__ blks, uint64_t *__restrict__ t_claim,
+                                                            uint64_t *__restrict__ t_done)
 {
     using C = typename Vec<T>::C;
     constexpr int M = LOG_E + LOG_T;
@@ -86,7 +88,7 @@ __global__ __launch_bounds__(1 << LOG_T, MINW) void k_batch(T *__restrict__ pool
                 for (int p = bc.pass_begin; p < bc.pass_end; ++p) {
                     const SPass pass = ldc<SPass>(as_const(passes) + p);
                     for (uint64_t b = 0; b < nblocks; ++b)
-                        item_block<T, LOG_E, LOG_T, FORM>(a, pass, b, as_const(stages), as_const(rounds), as_const(ops), lds,
+                        item_block<T, LOG_E, LOG_T, FORM>(a, pass, b, as_const(stages), as_const(rounds), as_const(ops), as_const(blks), lds,
                                                           p == bc.pass_begin);
                     // the next pass reads, from other threads of this workgroup, what this one wrote:
                     // a workgroup-scope barrier (release/acquire) orders it; all threads share the CU's L1
@@ -97,7 +99,7 @@ __global__ __launch_bounds__(1 << LOG_T, MINW) void k_batch(T *__restrict__ pool
         if (it.pass >= 0) {
             const SPass pass = ldc<SPass>(as_const(passes) + it.pass);
             for (uint64_t b = it.b0; b < it.b1; ++b)
-                item_block<T, LOG_E, LOG_T, FORM>(a, pass, b, as_const(stages), as_const(rounds), as_const(ops), lds,
+                item_block<T, LOG_E, LOG_T, FORM>(a, pass, b, as_const(stages), as_const(rounds), as_const(ops), as_const(blks), lds,
                                                   it.first != 0);
         }
         if (threadIdx.x == 0) {
@@ -139,6 +141,7 @@ struct qsim_batch {
     SStage *d_stages = nullptr;
     SRound *d_rounds = nullptr;
     SOp *d_ops = nullptr;
+    SBlk *d_blks = nullptr;
     uint64_t *d_tclaim = nullptr, *d_tdone = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
@@ -161,8 +164,8 @@ template <typename T, int LE, int LT, int MW, int FORM> int form_grid(int *grid)
 template <typename T, int LE, int LT, int MW, int FORM> int form_launch(qsim_batch *b, const BatchLaunch &l)
 {
     hipLaunchKernelGGL((k_batch<T, LE, LT, MW, FORM>), dim3(l.grid), dim3(1 << LT), 0, b->stream, static_cast<T *>(b->pool),
-                       b->d_circs, b->d_items + l.begin, l.count, b->d_passes, b->d_stages, b->d_rounds, b->d_ops, b->d_tclaim,
-                       b->d_tdone);
+                       b->d_circs, b->d_items + l.begin, l.count, b->d_passes, b->d_stages, b->d_rounds, b->d_ops, b->d_blks,
+                       b->d_tclaim, b->d_tdone);
     QSIM_HIP(hipGetLastError());
     return QSIM_OK;
 }
@@ -262,6 +265,7 @@ int qsim_batch_create(int count, const int *nqubits, const int64_t *offsets, con
     std::vector<SStage> stages;
     std::vector<SRound> rounds;
     std::vector<SOp> ops;
+    std::vector<SBlk> blks;
     uint64_t slot = 0;
     for (int c = 0; c < count; ++c) {
         BatchCirc bc{};
@@ -275,7 +279,7 @@ int qsim_batch_create(int count, const int *nqubits, const int64_t *offsets, con
             }
         b->total_gates += int64_t(gl.size());
         bc.pass_begin = int(passes.size());
-        if (int rc = staged_schedule(bc.n_eff, dtype, m, log_e, gl, passes, stages, rounds, ops)) {
+        if (int rc = staged_schedule(bc.n_eff, dtype, m, log_e, gl, passes, stages, rounds, ops, blks)) {
             delete b;
             return rc;
         }
@@ -350,6 +354,9 @@ int qsim_batch_create(int count, const int *nqubits, const int64_t *offsets, con
     if ((e = hipMalloc(&b->d_stages, sizeof(SStage) * std::max<size_t>(1, stages.size()))) != hipSuccess) return fail(e, "batch: tables");
     if ((e = hipMalloc(&b->d_rounds, sizeof(SRound) * std::max<size_t>(1, rounds.size()))) != hipSuccess) return fail(e, "batch: tables");
     if ((e = hipMalloc(&b->d_ops, sizeof(SOp) * std::max<size_t>(1, ops.size()))) != hipSuccess) return fail(e, "batch: tables");
+    if ((e = hipMalloc(&b->d_blks, sizeof(SBlk) * std::max<size_t>(1, blks.size()))) != hipSuccess) return fail(e, "batch: tables");
+    if (!blks.empty() && (e = hipMemcpy(b->d_blks, blks.data(), sizeof(SBlk) * blks.size(), hipMemcpyHostToDevice)) != hipSuccess)
+        return fail(e, "batch: upload");
     if ((e = hipMalloc(&b->d_tclaim, sizeof(uint64_t) * count)) != hipSuccess) return fail(e, "batch: timestamps");
     if ((e = hipMalloc(&b->d_tdone, sizeof(uint64_t) * count)) != hipSuccess) return fail(e, "batch: timestamps");
     if ((e = hipMemcpy(b->d_circs, b->circs.data(), sizeof(BatchCirc) * count, hipMemcpyHostToDevice)) != hipSuccess) return fail(e, "batch: upload");
@@ -473,6 +480,7 @@ int qsim_batch_free(qsim_batch *b)
     free_dev(b->d_stages);
     free_dev(b->d_rounds);
     free_dev(b->d_ops);
+    free_dev(b->d_blks);
     free_dev(b->d_tclaim);
     free_dev(b->d_tdone);
     delete b;

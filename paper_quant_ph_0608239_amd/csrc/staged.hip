@@ -21,6 +21,7 @@
 #include <array>
 #include <cstring>
 #include <cmath>
+#include <complex>
 
 #include "qsim_internal.h"
 
@@ -39,12 +40,14 @@ namespace {
 template <typename T, int LOG_E, int LOG_T, int MINW>
 __global__ __launch_bounds__(1 << LOG_T, MINW) void k_staged(T *__restrict__ a, const SPass *__restrict__ passp,
                                                              const SStage *__restrict__ stages, const SRound *__restrict__ rounds,
-                                                             const SOp *__restrict__ ops, int init_zero)
+                                                             const SOp *__restrict__ ops, const SBlk *__restrict__ blks,
+                                                             int init_zero)
 {
     using C = typename Vec<T>::C;
     __shared__ C lds[lds_slots<T>(LOG_E + LOG_T)];
     const SPass pass = ldc<SPass>(as_const(passp));
-    run_block<T, LOG_E, LOG_T>(a, pass, blockIdx.x, as_const(stages), as_const(rounds), as_const(ops), lds, init_zero != 0);
+    run_block<T, LOG_E, LOG_T>(a, pass, blockIdx.x, as_const(stages), as_const(rounds), as_const(ops), as_const(blks), lds,
+                               init_zero != 0);
 }
 
 // The same pass with a buffer of half the block (every LDS round trip in two halves): twice the
@@ -53,12 +56,13 @@ template <typename T, int LOG_E, int LOG_T, int MINW>
 __global__ __launch_bounds__(1 << LOG_T, MINW) void k_staged_half(T *__restrict__ a, const SPass *__restrict__ passp,
                                                                   const SStage *__restrict__ stages,
                                                                   const SRound *__restrict__ rounds,
-                                                                  const SOp *__restrict__ ops, int init_zero)
+                                                                  const SOp *__restrict__ ops, const SBlk *__restrict__ blks,
+                                                                  int init_zero)
 {
     using C = typename Vec<T>::C;
     __shared__ C lds[lds_slots<T>(LOG_E + LOG_T - 1)];
     const SPass pass = ldc<SPass>(as_const(passp));
-    run_block_half<T, LOG_E, LOG_T>(a, pass, blockIdx.x, as_const(stages), as_const(rounds), as_const(ops), lds,
+    run_block_half<T, LOG_E, LOG_T>(a, pass, blockIdx.x, as_const(stages), as_const(rounds), as_const(ops), as_const(blks), lds,
                                     init_zero != 0);
 }
 
@@ -68,12 +72,13 @@ template <typename T, int LOG_E, int LOG_T, int MINW>
 __global__ __launch_bounds__(1 << LOG_T, MINW) void k_staged_wave(T *__restrict__ a, const SPass *__restrict__ passp,
                                                                   const SStage *__restrict__ stages,
                                                                   const SRound *__restrict__ rounds,
-                                                                  const SOp *__restrict__ ops, int init_zero)
+                                                                  const SOp *__restrict__ ops, const SBlk *__restrict__ blks,
+                                                                  int init_zero)
 {
     using C = typename Vec<T>::C;
     __shared__ C lds[lds_slots<T>(LOG_E + LOG_T - 1)];
     const SPass pass = ldc<SPass>(as_const(passp));
-    run_block_wave<T, LOG_E, LOG_T>(a, pass, blockIdx.x, as_const(stages), as_const(rounds), as_const(ops), lds,
+    run_block_wave<T, LOG_E, LOG_T>(a, pass, blockIdx.x, as_const(stages), as_const(rounds), as_const(ops), as_const(blks), lds,
                                     init_zero != 0);
 }
 
@@ -114,6 +119,7 @@ struct StagedPlan {
     SStage *d_stages = nullptr;
     SRound *d_rounds = nullptr;
     SOp *d_ops = nullptr;
+    SBlk *d_blks = nullptr;
 };
 
 namespace {
@@ -303,11 +309,18 @@ struct HOp {
     double m[8];        // dense 2x2, or diag d0 = m[0..1], d1 = m[2..3]
     double theta[2];
     int angles;
+    int pair = -1;      // a two-qubit block: its index in the stage's block list (dense is false)
+    int lb2 = -1;       // a two-qubit block: local bit of its higher-ranked register bit (lb: the lower)
 };
+
+// ordering key of the flip list: after the register-bit lists and the pair lists (the diagonal list
+// follows it)
+constexpr int flip_key_of(int log_e) { return kLists * log_e + npairs(log_e); }
 
 // two ops of a stage may run in either order
 bool commute(const HOp &a, const HOp &b)
 {
+    if (a.pair >= 0 || b.pair >= 0) return (a.qmask & b.qmask) == 0;
     if (!a.dense && !b.dense) return true;
     if (a.dense && !b.dense) return !((b.qmask >> a.target) & 1);
     if (!a.dense && b.dense) return !((a.qmask >> b.target) & 1);
@@ -361,9 +374,167 @@ static void order_threads(SStage &cur, uint32_t rbset, int m, int log_e, int dty
 // element masks) and its thread part, and order the ops into rounds. An op goes to the earliest
 // round in which it runs after every earlier op of the stage it does not commute with (within a
 // round: bit 0 ops, ..., bit LOG_E-1 ops, unconditional before conditional, then diagonal ops).
+// Two-qubit blocks of a stage. Walking the ops in circuit order, each register bit may belong to one
+// open block: a single-qubit block (the ops on that bit alone so far) or a pair block (ops on that bit
+// and one other register bit). An unconditional single-qubit op joins its bit's block or opens one; a
+// two-qubit diagonal op (CZ, a controlled phase with a given factor) on two register bits joins their
+// common pair block, or opens a pair block that takes in both bits' single-qubit blocks; if either bit
+// is in a pair block with a third bit, it closes both bits' blocks and stays a separate op. Any other
+// op closes the blocks of every register bit it touches. A closed block is placed where it closes: every op between one of its members and that
+// place touches neither of its bits (it would have joined or closed the block), so it commutes with
+// the members. A pair block with at least three dense members is multiplied into one 4x4 (FP64, in
+// member order); any other block keeps its members as separate ops.
+static std::vector<HOp> form_pair_blocks(const std::vector<HOp> &sops, uint32_t rbset, int m, const int *localof,
+                                         const std::function<int(int)> &rank_of,
+                                         std::vector<std::array<std::complex<double>, 16>> &mats)
+{
+    using cd = std::complex<double>;
+    const size_t N = sops.size();
+    auto regbits_of = [&](const HOp &h) {  // local register bits the op touches, or ~0u if it touches
+        uint32_t lb = 0;                  // a non-resident qubit or a thread bit
+        for (int q = 0; q < 64; ++q)
+            if ((h.qmask >> q) & 1) {
+                const int l = localof[q];
+                if (l < 0 || !((rbset >> l) & 1)) return ~0u;
+                lb |= 1u << l;
+            }
+        return lb;
+    };
+    auto blockable = [&](const HOp &h, uint32_t lb) {
+        if (lb == ~0u || h.gcm != 0) return false;
+        if (h.dense) return h.controls == 0 && __builtin_popcount(lb) == 1;
+        return h.angles == 0 && __builtin_popcount(lb) <= 2;
+    };
+    struct Blk {
+        uint32_t bits;
+        std::vector<size_t> members;
+        bool merged = false;
+    };
+    std::vector<Blk> blks;
+    std::vector<int> owner(size_t(m), -1);
+    std::vector<std::pair<long, int>> order;  // (op index, -1) or (-1, block index)
+    auto close = [&](int id) {
+        order.push_back({-1, id});
+        for (int l = 0; l < m; ++l)
+            if (owner[size_t(l)] == id) owner[size_t(l)] = -1;
+    };
+    for (size_t xi = 0; xi < N; ++xi) {
+        const HOp &h = sops[xi];
+        const uint32_t lb = regbits_of(h);
+        if (!blockable(h, lb)) {
+            for (int q = 0; q < 64; ++q)
+                if ((h.qmask >> q) & 1) {
+                    const int l = localof[q];
+                    if (l >= 0 && owner[size_t(l)] >= 0) close(owner[size_t(l)]);
+                }
+            order.push_back({long(xi), -1});
+            continue;
+        }
+        if (__builtin_popcount(lb) == 1) {
+            const int l = __builtin_ctz(lb);
+            if (owner[size_t(l)] < 0) {
+                blks.push_back(Blk{lb, {}});
+                owner[size_t(l)] = int(blks.size()) - 1;
+            }
+            blks[size_t(owner[size_t(l)])].members.push_back(xi);
+            continue;
+        }
+        const int a = __builtin_ctz(lb), b = 31 - __builtin_clz(lb);
+        int oa = owner[size_t(a)], ob = owner[size_t(b)];
+        if (oa >= 0 && oa == ob) {
+            blks[size_t(oa)].members.push_back(xi);
+            continue;
+        }
+        auto is_pair = [&](int o) { return o >= 0 && __builtin_popcount(blks[size_t(o)].bits) == 2; };
+        if (is_pair(oa) || is_pair(ob)) {
+            // a two-qubit op across two blocks ends them both and runs on its own (on a layered circuit
+            // each pair block then spans two single-qubit layers around its own two-qubit op)
+            if (oa >= 0) close(oa);
+            if (ob >= 0) close(ob);
+            order.push_back({long(xi), -1});
+            continue;
+        }
+        Blk nb{lb, {}};
+        for (int o : {oa, ob})
+            if (o >= 0) {
+                nb.members.insert(nb.members.end(), blks[size_t(o)].members.begin(), blks[size_t(o)].members.end());
+                blks[size_t(o)].merged = true;
+            }
+        std::sort(nb.members.begin(), nb.members.end());
+        nb.members.push_back(xi);
+        blks.push_back(nb);
+        owner[size_t(a)] = owner[size_t(b)] = int(blks.size()) - 1;
+    }
+    for (int l = 0; l < m; ++l)
+        if (owner[size_t(l)] >= 0) close(owner[size_t(l)]);
+
+    std::vector<HOp> out;
+    for (const auto &o : order) {
+        if (o.first >= 0) {
+            out.push_back(sops[size_t(o.first)]);
+            continue;
+        }
+        const Blk &bk = blks[size_t(o.second)];
+        if (bk.merged) continue;
+        int ndense = 0;
+        for (size_t xi : bk.members) ndense += sops[xi].dense;
+        if (__builtin_popcount(bk.bits) != 2 || ndense < 3) {
+            for (size_t xi : bk.members) out.push_back(sops[xi]);
+            continue;
+        }
+        // the block's 4x4: p = bit of the lower-ranked register bit + 2 * bit of the higher one
+        const int la = __builtin_ctz(bk.bits), lb2 = 31 - __builtin_clz(bk.bits);
+        const int lo_l = rank_of(la) < rank_of(lb2) ? la : lb2, hi_l = lo_l == la ? lb2 : la;
+        std::array<cd, 16> M{};
+        for (int p = 0; p < 4; ++p) M[size_t(5 * p)] = 1.0;
+        uint64_t qm = 0;
+        for (size_t xi : bk.members) {
+            const HOp &h = sops[xi];
+            qm |= h.qmask;
+            std::array<cd, 16> G{};
+            auto bitof = [&](int p, int l) { return l == lo_l ? (p & 1) : ((p >> 1) & 1); };
+            if (h.dense) {
+                const int t = localof[h.target];
+                const cd u[2][2] = {{cd(h.m[0], h.m[1]), cd(h.m[2], h.m[3])}, {cd(h.m[4], h.m[5]), cd(h.m[6], h.m[7])}};
+                const int o = t == lo_l ? hi_l : lo_l;
+                for (int po = 0; po < 4; ++po)
+                    for (int pi = 0; pi < 4; ++pi)
+                        if (bitof(po, o) == bitof(pi, o)) G[size_t(4 * po + pi)] = u[bitof(po, t)][bitof(pi, t)];
+            } else {
+                const int t = localof[h.target];
+                const cd d0(h.m[0], h.m[1]), d1(h.m[2], h.m[3]);
+                for (int p = 0; p < 4; ++p) {
+                    bool cond = true;  // controls of a diagonal op are register bits of this pair
+                    for (int q = 0; q < 64; ++q)
+                        if (((h.controls >> q) & 1) && !bitof(p, localof[q])) cond = false;
+                    G[size_t(5 * p)] = cond ? (bitof(p, t) ? d1 : d0) : cd(1.0);
+                }
+            }
+            std::array<cd, 16> P{};
+            for (int r = 0; r < 4; ++r)
+                for (int c = 0; c < 4; ++c) {
+                    cd acc = 0.0;
+                    for (int k = 0; k < 4; ++k) acc += G[size_t(4 * r + k)] * M[size_t(4 * k + c)];
+                    P[size_t(4 * r + c)] = acc;
+                }
+            M = P;
+        }
+        HOp hb{};
+        hb.dense = false;
+        hb.pair = int(mats.size());
+        hb.lb = lo_l;
+        hb.target = -1;
+        hb.qmask = qm;
+        hb.lb2 = hi_l;
+        mats.push_back(M);
+        out.push_back(hb);
+    }
+    return out;
+}
+
 static void emit_stage(SStage cur, uint32_t rbset, int log_e, int m, int dtype, const int *localof, const uint8_t *R,
-                       const std::vector<HOp> &sops, std::vector<SStage> &stages, std::vector<SRound> &rounds,
-                       std::vector<SOp> &ops)
+                       const std::vector<HOp> &sops_in, std::vector<SStage> &stages, std::vector<SRound> &rounds,
+                       std::vector<SOp> &ops, std::vector<SBlk> &blks_out)
 {
     const int E = 1 << log_e;
     int nrb = __builtin_popcount(rbset);
@@ -378,6 +549,8 @@ static void emit_stage(SStage cur, uint32_t rbset, int log_e, int m, int dtype, 
     order_threads(cur, rbset, m, log_e, dtype, R, 0, nullptr, nullptr);
     for (int j = 0; j < log_e; ++j) cur.prb[j] = R[cur.rb[j]];
     auto rank_of = [&](int lb) { return __builtin_popcount(rbset & ((1u << lb) - 1)); };
+    std::vector<std::array<std::complex<double>, 16>> mats;
+    const std::vector<HOp> sops = form_pair_blocks(sops_in, rbset, m, localof, rank_of, mats);
     const size_t N = sops.size();
     std::vector<SOp> rec(N);
     std::vector<int> key(N), round(N);
@@ -396,7 +569,9 @@ static void emit_stage(SStage cur, uint32_t rbset, int log_e, int m, int dtype, 
         o.theta[0] = h.theta[0];
         o.theta[1] = h.theta[1];
         memcpy(o.m, h.m, sizeof(o.m));
-        if (h.dense) {
+        if (h.pair >= 0) {
+            key[xi] = kLists * log_e + pair_index(log_e, rank_of(h.lb), rank_of(h.lb2));
+        } else if (h.dense) {
             const int j = rank_of(h.lb);
             for (int p = 0; p < E / 2; ++p) {
                 const int r = (p & ((1 << j) - 1)) | ((p >> j) << (j + 1));
@@ -432,7 +607,7 @@ static void emit_stage(SStage cur, uint32_t rbset, int log_e, int m, int dtype, 
             // a sign flip: d0 = 1 and d1 = -1 exactly, with the target folded into the condition
             const bool flip = d0_one && h.angles == 0 && h.m[2] == -1.0 && h.m[3] == 0.0 && o.m0 == 0 && o.lt < 0 &&
                               o.gtb == 0;
-            key[xi] = kLists * log_e + (flip ? 0 : 1);
+            key[xi] = flip_key_of(log_e) + (flip ? 0 : 1);
         }
         int k = 0;
         for (size_t y = 0; y < xi; ++y)
@@ -446,7 +621,7 @@ static void emit_stage(SStage cur, uint32_t rbset, int log_e, int m, int dtype, 
     // (other qubit a register bit), per lane (a thread bit) or per block (a non-resident bit). Every
     // op executed between the dense op and the flip's place commutes with the flip, so the order
     // of non-commuting operations is unchanged.
-    const int flip_key = kLists * log_e;
+    const int flip_key = flip_key_of(log_e);
     std::vector<char> gone(N, 0);
     auto bit_of_key = [&](int kk) { return kk / kLists; };
     // condition of a fused flip on the qubit other than the dense op's target
@@ -475,6 +650,12 @@ static void emit_stage(SStage cur, uint32_t rbset, int log_e, int m, int dtype, 
             key[d] = kLists * j + kListBlockFlip;
         }
     };
+    // a two-qubit block on one of the qubits q2 in rounds [r0, r1)
+    auto pair_between = [&](int r0, int r1, uint64_t q2) {
+        for (size_t yi = 0; yi < N; ++yi)
+            if (sops[yi].pair >= 0 && round[yi] >= r0 && round[yi] < r1 && (sops[yi].qmask & q2)) return true;
+        return false;
+    };
     // the only dense op of its round on its register bit
     auto alone = [&](size_t d) {
         const int j = bit_of_key(key[d]);
@@ -495,6 +676,8 @@ static void emit_stage(SStage cur, uint32_t rbset, int log_e, int m, int dtype, 
         if (best < 0) continue;
         const size_t d = size_t(best);
         if (key[d] % kLists != 0 || !alone(d)) continue;  // only a plain unconditional op takes a flip
+        // the round's two-qubit blocks run after its single-bit lists and before its flips
+        if (pair_between(round[xi], round[xi] + 1, q2)) continue;
         set_alt(d, q2, bit_of_key(key[d]), false);
         gone[xi] = 1;
     }
@@ -513,17 +696,38 @@ static void emit_stage(SStage cur, uint32_t rbset, int log_e, int m, int dtype, 
         if (best < 0) continue;
         const size_t d = size_t(best);
         if (key[d] % kLists != 0 || !alone(d)) continue;
+        if (pair_between(round[xi] + 1, round[d], q2)) continue;
         set_alt(d, q2, bit_of_key(key[d]), true);
         gone[xi] = 1;
     }
     cur.round_begin = int(rounds.size());
+    // keys: register-bit lists, then pair lists, then flips and diagonal ops; the pair lists go to
+    // pseg (block table), everything else to seg (op table)
+    const int fk = flip_key_of(log_e);
     for (int k = 0; k < nrounds; ++k) {
         SRound rd{};
-        for (int list = 0; list <= kLists * log_e + 1; ++list) {
-            rd.seg[list] = int(ops.size());
-            for (size_t xi = 0; xi < N; ++xi)
-                if (!gone[xi] && round[xi] == k && key[xi] == list) ops.push_back(rec[xi]);
+        for (int list = 0; list <= fk + 1; ++list) {
+            const bool pl = list >= kLists * log_e && list < fk;
+            if (pl) rd.pseg[list - kLists * log_e] = int(blks_out.size());
+            else rd.seg[list < fk ? list : list - npairs(log_e)] = int(ops.size());
+            for (size_t xi = 0; xi < N; ++xi) {
+                if (gone[xi] || round[xi] != k || key[xi] != list) continue;
+                if (pl) {
+                    SBlk b{};
+                    const auto &M = mats[size_t(sops[xi].pair)];
+                    for (int e = 0; e < 16; ++e) {
+                        b.m[2 * e] = M[size_t(e)].real();
+                        b.m[2 * e + 1] = M[size_t(e)].imag();
+                        b.mf[2 * e] = float(b.m[2 * e]);
+                        b.mf[2 * e + 1] = float(b.m[2 * e + 1]);
+                    }
+                    blks_out.push_back(b);
+                } else {
+                    ops.push_back(rec[xi]);
+                }
+            }
         }
+        rd.pseg[npairs(log_e)] = int(blks_out.size());
         rd.seg[kLists * log_e + 2] = int(ops.size());
         rounds.push_back(rd);
     }
@@ -657,7 +861,7 @@ static bool assign_half(SPass &ps, std::vector<SStage> &stages, int m, int log_e
 
 int staged::staged_schedule(int n, int dtype, int m, int log_e, const std::vector<qsim_gate> &gates,
                             std::vector<SPass> &passes, std::vector<SStage> &stages, std::vector<SRound> &rounds,
-                            std::vector<SOp> &ops)
+                            std::vector<SOp> &ops, std::vector<SBlk> &blks)
 {
     if (m > kMaxM || log_e < 1 || log_e > kMaxLogE || m - log_e > kMaxLogT || m - log_e < 0)
         return set_error(QSIM_EINVAL, "staged: block shape outside the kernel tables");
@@ -793,7 +997,7 @@ int staged::staged_schedule(int n, int dtype, int m, int log_e, const std::vecto
             uint32_t rbset = 0;
             int nrb = 0;
             auto close_stage = [&]() {
-                emit_stage(cur, rbset, log_e, m, dtype, localof, ps.R, sops, stages, rounds, ops);
+                emit_stage(cur, rbset, log_e, m, dtype, localof, ps.R, sops, stages, rounds, ops, blks);
                 sops.clear();
                 cur = SStage{};
                 cur.swap_p = cur.swap_q = -1;
@@ -875,7 +1079,7 @@ int staged::staged_schedule(int n, int dtype, int m, int log_e, const std::vecto
                 }
                 SStage cur{};
                 cur.swap_p = cur.swap_q = -1;
-                emit_stage(cur, rbset, log_e, m, dtype, localof, ps.R, sops, stages, rounds, ops);
+                emit_stage(cur, rbset, log_e, m, dtype, localof, ps.R, sops, stages, rounds, ops, blks);
                 rem.swap(rest);
             }
         }
@@ -915,7 +1119,8 @@ int staged_build(int n, int dtype, const std::vector<qsim_gate> &gates, int lds_
     std::vector<SStage> stages;
     std::vector<SRound> rounds;
     std::vector<SOp> ops;
-    if (int rc = staged_schedule(n, dtype, m, log_e, gates, passes, stages, rounds, ops)) return rc;
+    std::vector<SBlk> blks;
+    if (int rc = staged_schedule(n, dtype, m, log_e, gates, passes, stages, rounds, ops, blks)) return rc;
     StagedPlan *p = new StagedPlan();
     p->n = n;
     p->dtype = dtype;
@@ -928,6 +1133,8 @@ int staged_build(int n, int dtype, const std::vector<qsim_gate> &gates, int lds_
     if (e == hipSuccess) e = hipMalloc(&p->d_stages, sizeof(SStage) * std::max<size_t>(1, stages.size()));
     if (e == hipSuccess) e = hipMalloc(&p->d_rounds, sizeof(SRound) * std::max<size_t>(1, rounds.size()));
     if (e == hipSuccess) e = hipMalloc(&p->d_ops, sizeof(SOp) * std::max<size_t>(1, ops.size()));
+    if (e == hipSuccess) e = hipMalloc(&p->d_blks, sizeof(SBlk) * std::max<size_t>(1, blks.size()));
+    if (e == hipSuccess && !blks.empty()) e = hipMemcpy(p->d_blks, blks.data(), sizeof(SBlk) * blks.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(p->d_passes, passes.data(), sizeof(SPass) * passes.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess && !stages.empty())
         e = hipMemcpy(p->d_stages, stages.data(), sizeof(SStage) * stages.size(), hipMemcpyHostToDevice);
@@ -958,21 +1165,21 @@ template <typename T, int LE, int LT, int MW>
 static void launch_variant(StagedPlan *p, qsim_state *s, size_t i, int init_zero)
 {
     hipLaunchKernelGGL((k_staged<T, LE, LT, MW>), dim3(unsigned(dim(p->n - p->m))), dim3(1 << LT), 0, s->stream,
-                       static_cast<T *>(s->data), p->d_passes + i, p->d_stages, p->d_rounds, p->d_ops, init_zero);
+                       static_cast<T *>(s->data), p->d_passes + i, p->d_stages, p->d_rounds, p->d_ops, p->d_blks, init_zero);
 }
 
 template <typename T, int LE, int LT, int MW>
 static void launch_half(StagedPlan *p, qsim_state *s, size_t i, int init_zero)
 {
     hipLaunchKernelGGL((k_staged_half<T, LE, LT, MW>), dim3(unsigned(dim(p->n - p->m))), dim3(1 << LT), 0, s->stream,
-                       static_cast<T *>(s->data), p->d_passes + i, p->d_stages, p->d_rounds, p->d_ops, init_zero);
+                       static_cast<T *>(s->data), p->d_passes + i, p->d_stages, p->d_rounds, p->d_ops, p->d_blks, init_zero);
 }
 
 template <typename T, int LE, int LT, int MW>
 static void launch_wave(StagedPlan *p, qsim_state *s, size_t i, int init_zero)
 {
     hipLaunchKernelGGL((k_staged_wave<T, LE, LT, MW>), dim3(unsigned(dim(p->n - p->m))), dim3(1 << LT), 0, s->stream,
-                       static_cast<T *>(s->data), p->d_passes + i, p->d_stages, p->d_rounds, p->d_ops, init_zero);
+                       static_cast<T *>(s->data), p->d_passes + i, p->d_stages, p->d_rounds, p->d_ops, p->d_blks, init_zero);
 }
 
 // the kernel that runs pass i: the wave-split kernel where every round trip splits at a wave position
@@ -1086,6 +1293,7 @@ void staged_free(StagedPlan *p)
     if (p->d_stages) (void)hipFree(p->d_stages);
     if (p->d_rounds) (void)hipFree(p->d_rounds);
     if (p->d_ops) (void)hipFree(p->d_ops);
+    if (p->d_blks) (void)hipFree(p->d_blks);
     delete p;
 }
 

@@ -47,8 +47,24 @@ struct SOp {
 // equals circuit order.
 constexpr int kLists = 8;
 constexpr int kListBlockFlip = 1, kListPairFlip = 2, kListLaneFlip = 6, kListCond = 7;
+// After the register-bit lists, a round runs one list of two-qubit blocks per pair of register bits
+// (ja < jb, numbered ja-major: (0,1), (0,2), ..., (1,2), ...): [pseg[p], pseg[p + 1]) in the block
+// table. Then come the sign flips and the other diagonal ops of the op table.
+constexpr int kMaxPairs = kMaxLogE * (kMaxLogE - 1) / 2;
+constexpr int npairs(int log_e) { return log_e * (log_e - 1) / 2; }
+constexpr int pair_index(int log_e, int ja, int jb) { return ja * (2 * log_e - ja - 1) / 2 + (jb - ja - 1); }
 struct SRound {
     int32_t seg[kLists * kMaxLogE + 4];
+    int32_t pseg[kMaxPairs + 1];
+};
+
+// A two-qubit block: a run of a stage's ops that act only on two register bits ja < jb, multiplied into
+// one 4x4 unitary (row-major complex, index p = bit ja + 2 bit jb) applied to each group of four
+// register elements. A 4x4 costs 16 multiply-adds per amplitude where the four or more single-qubit
+// 2x2s it replaces cost 6 each.
+struct SBlk {
+    double m[32];
+    float mf[32];  // m rounded to FP32 (complex64 kernels), filled by the scheduler
 };
 
 struct SStage {
@@ -374,6 +390,80 @@ __device__ __forceinline__ void op_flip(typename Vec<T>::C *x, const SOp &op, ui
 // the i-th register bit other than J
 constexpr int other_bit(int J, int i) { return i < J ? i : i + 1; }
 
+template <typename T> __device__ __forceinline__ const T *coefb(const SBlk &b);
+template <> __device__ __forceinline__ const double *coefb<double>(const SBlk &b) { return b.m; }
+template <> __device__ __forceinline__ const float *coefb<float>(const SBlk &b) { return b.mf; }
+
+// A two-qubit block on register bits JA < JB, in place: for each group of four elements, every output
+// is first summed over the three inputs other than its own (P_r), then its own input's term is added
+// into that input's registers (the input is no longer needed by any other output). 16 multiply-adds
+// per amplitude, no register copies; the 4x4 is wave-uniform.
+template <typename T, int E, int JA, int JB>
+__device__ __forceinline__ void op_pair(typename Vec<T>::C *x, const SBlk &b)
+{
+    const T *c = coefb<T>(b);
+    T mr[16], mi[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        mr[k] = c[2 * k];
+        mi[k] = c[2 * k + 1];
+    }
+#pragma unroll
+    for (int g = 0; g < E / 4; ++g) {
+        // element index of group g: g's bits with zeros inserted at JA and JB
+        const int lo = g & ((1 << JA) - 1);
+        const int mid = (g >> JA) & ((1 << (JB - JA - 1)) - 1);
+        const int hi = g >> (JB - 1);
+        const int r0 = lo | (mid << (JA + 1)) | (hi << (JB + 1));
+        const int id[4] = {r0, r0 | (1 << JA), r0 | (1 << JB), r0 | (1 << JA) | (1 << JB)};
+        T pr[4], pi[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            bool first = true;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                if (q == r) continue;
+                const T ar = mr[4 * r + q], ai = mi[4 * r + q];
+                const T xr = x[id[q]].x, xi = x[id[q]].y;
+                if (first) {
+                    pr[r] = ar * xr;
+                    pi[r] = ar * xi;
+                    pr[r] = fmat(-ai, xi, pr[r]);
+                    pi[r] = fmat(ai, xr, pi[r]);
+                    first = false;
+                } else {
+                    pr[r] = fmat(ar, xr, pr[r]);
+                    pi[r] = fmat(ar, xi, pi[r]);
+                    pr[r] = fmat(-ai, xi, pr[r]);
+                    pi[r] = fmat(ai, xr, pi[r]);
+                }
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const T dr = mr[5 * r], di = mi[5 * r];
+            typename Vec<T>::C &v = x[id[r]];
+            const T sre = fmat(-di, v.y, pr[r]);
+            const T sim = fmat(di, v.x, pi[r]);
+            fma_into<true>(v.y, dr, sim);
+            fma_into<true>(v.x, dr, sre);
+        }
+    }
+}
+
+// the pair list of register bits (JA, JB), if the stage has that pair
+template <typename T, int E, int LOG_E, int JA, int JB>
+__device__ __forceinline__ void pair_list(typename Vec<T>::C *x, const SRound &rd, cptr<SBlk> blks)
+{
+    if constexpr (JB < LOG_E) {
+        constexpr int s = pair_index(LOG_E, JA, JB);
+        for (int bi = rd.pseg[s]; bi < rd.pseg[s + 1]; ++bi) {
+            const SBlk b = ldc<SBlk>(blks + bi);
+            op_pair<T, E, JA, JB>(x, b);
+        }
+    }
+}
+
 // the per-pair flip list i of register bit J (flips by register bit other_bit(J, i))
 template <typename T, int E, int J, int I>
 __device__ __forceinline__ void pair_flip_list(typename Vec<T>::C *x, const SRound &rd, cptr<SOp> ops)
@@ -421,7 +511,7 @@ __device__ __forceinline__ void round_bit(typename Vec<T>::C *x, const SRound &r
 // all rounds of a stage on the registers x (in the stage's layout; et: the thread's local index part)
 template <typename T, int LOG_E>
 __device__ __forceinline__ void run_rounds(typename Vec<T>::C *x, const SStage &st, cptr<SRound> rounds, cptr<SOp> ops,
-                                           uint32_t et, uint64_t base)
+                                           cptr<SBlk> blks, uint32_t et, uint64_t base)
 {
     constexpr int E = 1 << LOG_E;
     for (int ri = st.round_begin; ri < st.round_end; ++ri) {
@@ -431,6 +521,19 @@ __device__ __forceinline__ void run_rounds(typename Vec<T>::C *x, const SStage &
         round_bit<T, E, 2>(x, rd, ops, et, base);
         if constexpr (LOG_E > 3) round_bit<T, E, (LOG_E > 3 ? 3 : 0)>(x, rd, ops, et, base);
         if constexpr (LOG_E > 4) round_bit<T, E, (LOG_E > 4 ? 4 : 0)>(x, rd, ops, et, base);
+        // the two-qubit blocks: one test skips all pair lists of a round without blocks
+        if (rd.pseg[0] != rd.pseg[npairs(LOG_E)]) {
+            pair_list<T, E, LOG_E, 0, 1>(x, rd, blks);
+            pair_list<T, E, LOG_E, 0, 2>(x, rd, blks);
+            pair_list<T, E, LOG_E, 0, 3>(x, rd, blks);
+            pair_list<T, E, LOG_E, 0, 4>(x, rd, blks);
+            pair_list<T, E, LOG_E, 1, 2>(x, rd, blks);
+            pair_list<T, E, LOG_E, 1, 3>(x, rd, blks);
+            pair_list<T, E, LOG_E, 1, 4>(x, rd, blks);
+            pair_list<T, E, LOG_E, 2, 3>(x, rd, blks);
+            pair_list<T, E, LOG_E, 2, 4>(x, rd, blks);
+            pair_list<T, E, LOG_E, 3, 4>(x, rd, blks);
+        }
         for (int oi = rd.seg[kLists * LOG_E]; oi < rd.seg[kLists * LOG_E + 1]; ++oi) {
             const SOp op = ldc<SOp>(ops + oi);
             if ((base & op.gcm) != op.gcm) continue;
@@ -516,7 +619,7 @@ __device__ __forceinline__ void store_block(T *__restrict__ a, const SPass &pass
 // back (permuted by the stage-end quantum swap, if any).
 template <typename T, int LOG_E, int LOG_T>
 __device__ __forceinline__ void run_stages(T *__restrict__ a, const SPass &pass, uint64_t base, cptr<SStage> stages,
-                                           cptr<SRound> rounds, cptr<SOp> ops,
+                                           cptr<SRound> rounds, cptr<SOp> ops, cptr<SBlk> blks,
                                            typename Vec<T>::C *lds, bool init_zero)
 {
     using C = typename Vec<T>::C;
@@ -569,7 +672,7 @@ __device__ __forceinline__ void run_stages(T *__restrict__ a, const SPass &pass,
 #pragma unroll
             for (int r = 0; r < E; ++r) x[r] = lds[ls + so[r]];
         }
-        run_rounds<T, LOG_E>(x, st, rounds, ops, et, base);
+        run_rounds<T, LOG_E>(x, st, rounds, ops, blks, et, base);
         if (out_mem) break;  // stored below, after the loop
         __syncthreads();  // every thread has read this stage's inputs before anyone overwrites LDS
         if (st.swap_p >= 0 && (base & st.swap_gcm) == st.swap_gcm) {
@@ -617,7 +720,7 @@ __device__ __forceinline__ void run_stages(T *__restrict__ a, const SPass &pass,
 // lds_slots<T>(LOG_E + LOG_T) amplitudes.
 template <typename T, int LOG_E, int LOG_T>
 __device__ __forceinline__ void run_block(T *__restrict__ a, const SPass &pass, uint64_t blk, cptr<SStage> stages,
-                                          cptr<SRound> rounds, cptr<SOp> ops,
+                                          cptr<SRound> rounds, cptr<SOp> ops, cptr<SBlk> blks,
                                           typename Vec<T>::C *lds, bool init_zero)
 {
     using C = typename Vec<T>::C;
@@ -640,7 +743,7 @@ __device__ __forceinline__ void run_block(T *__restrict__ a, const SPass &pass, 
         }
         __syncthreads();
     }
-    run_stages<T, LOG_E, LOG_T>(a, pass, base, stages, rounds, ops, lds, init_zero);
+    run_stages<T, LOG_E, LOG_T>(a, pass, base, stages, rounds, ops, blks, lds, init_zero);
     if (!(pass.direct & 2)) store_block<T, LOG_E, LOG_T>(a, pass, base, dt, lds);
     // a caller that runs the next block in this workgroup overwrites LDS: every thread must have
     // read its last values first
@@ -703,7 +806,7 @@ __device__ __forceinline__ void exchange_half(typename Vec<T>::C *x, typename Ve
 // trip split in two by the stages' split bits. `lds` holds lds_slots<T>(LOG_E + LOG_T - 1) amplitudes.
 template <typename T, int LOG_E, int LOG_T>
 __device__ __forceinline__ void run_block_half(T *__restrict__ a, const SPass &pass, uint64_t blk, cptr<SStage> stages,
-                                               cptr<SRound> rounds, cptr<SOp> ops, typename Vec<T>::C *lds,
+                                               cptr<SRound> rounds, cptr<SOp> ops, cptr<SBlk> blks, typename Vec<T>::C *lds,
                                                bool init_zero)
 {
     using C = typename Vec<T>::C;
@@ -755,7 +858,7 @@ __device__ __forceinline__ void run_block_half(T *__restrict__ a, const SPass &p
                             slot<T>(int(squeeze(et, st.hb_in))), so, st.hj_in, false);
     }
     for (int si = pass.stage_begin;;) {
-        run_rounds<T, LOG_E>(x, st, rounds, ops, et, base);
+        run_rounds<T, LOG_E>(x, st, rounds, ops, blks, et, base);
         if (++si == pass.stage_end) break;
         const SStage nx = ldc<SStage>(stages + si);
         uint32_t nt = 0;
@@ -844,7 +947,7 @@ __device__ __forceinline__ void wave_in(typename Vec<T>::C *x, const typename Ve
 // lds_slots<T>(LOG_E + LOG_T - 1) amplitudes.
 template <typename T, int LOG_E, int LOG_T>
 __device__ __forceinline__ void run_block_wave(T *__restrict__ a, const SPass &pass, uint64_t blk, cptr<SStage> stages,
-                                               cptr<SRound> rounds, cptr<SOp> ops, typename Vec<T>::C *lds,
+                                               cptr<SRound> rounds, cptr<SOp> ops, cptr<SBlk> blks, typename Vec<T>::C *lds,
                                                bool init_zero)
 {
     using C = typename Vec<T>::C;
@@ -900,7 +1003,7 @@ __device__ __forceinline__ void run_block_wave(T *__restrict__ a, const SPass &p
             half_slots<T, LOG_E>(st.rb, st.hb_in, so);
             wave_in<T, E>(x, lds, slot<T>(int(squeeze(et, st.hb_in))), so, st.hj_in);
         }
-        run_rounds<T, LOG_E>(x, st, rounds, ops, et, base);
+        run_rounds<T, LOG_E>(x, st, rounds, ops, blks, et, base);
         if (last) break;  // stored below, after the loop
         int so[E];
         half_slots<T, LOG_E>(st.rb, st.hb_out, so);
@@ -941,7 +1044,8 @@ __device__ __forceinline__ void run_block_wave(T *__restrict__ a, const SPass &p
 
 // host: append the schedule of one circuit (see staged.hip)
 int staged_schedule(int n, int dtype, int m, int log_e, const std::vector<qsim_gate> &gates, std::vector<SPass> &passes,
-                    std::vector<SStage> &stages, std::vector<SRound> &rounds, std::vector<SOp> &ops);
+                    std::vector<SStage> &stages, std::vector<SRound> &rounds, std::vector<SOp> &ops,
+                    std::vector<SBlk> &blks);
 bool staged_variant_ok(int dtype, int log_e, int log_t);
 __global__ void k_op_angles(SOp *ops, int nops);
 

@@ -1,7 +1,7 @@
 // Test helper (host only): run the staged scheduler of libqsim on a gate list and write its tables, so
 // that a CPU test can check them. Usage: sched_dump <gates.bin> <n> <dtype> <m> <log_e> <out.bin>.
-// gates.bin holds qsim_gate records; out.bin holds the four record sizes, the four table lengths and
-// the pass, stage, round and op tables.
+// gates.bin holds qsim_gate records; out.bin holds the five record sizes, the five table lengths and
+// the pass, stage, round, op and two-qubit block tables.
 #include <cstdint>
 #include <cstdio>
 #include <cstdlib>
@@ -27,21 +27,23 @@ int main(int argc, char **argv)
     std::vector<SStage> stages;
     std::vector<SRound> rounds;
     std::vector<SOp> ops;
+    std::vector<SBlk> blks;
     const int rc = staged_schedule(std::atoi(argv[2]), std::atoi(argv[3]), std::atoi(argv[4]), std::atoi(argv[5]), gates,
-                                   passes, stages, rounds, ops);
+                                   passes, stages, rounds, ops, blks);
     if (rc) {
         std::printf("rc=%d\n", rc);
         return 1;
     }
     std::FILE *o = std::fopen(argv[6], "wb");
     if (!o) return 2;
-    const uint64_t head[8] = {sizeof(SPass), sizeof(SStage), sizeof(SRound), sizeof(SOp),
-                              passes.size(), stages.size(), rounds.size(), ops.size()};
+    const uint64_t head[10] = {sizeof(SPass), sizeof(SStage), sizeof(SRound), sizeof(SOp), sizeof(SBlk),
+                               passes.size(), stages.size(), rounds.size(), ops.size(), blks.size()};
     std::fwrite(head, sizeof head, 1, o);
     std::fwrite(passes.data(), sizeof(SPass), passes.size(), o);
     std::fwrite(stages.data(), sizeof(SStage), stages.size(), o);
     std::fwrite(rounds.data(), sizeof(SRound), rounds.size(), o);
     std::fwrite(ops.data(), sizeof(SOp), ops.size(), o);
+    std::fwrite(blks.data(), sizeof(SBlk), blks.size(), o);
     std::fclose(o);
     return 0;
 }

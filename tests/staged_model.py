@@ -23,22 +23,33 @@ PASS = np.dtype([('m', '<i4'), ('sb', '<i4'), ('se', '<i4'), ('direct', '<i4'), 
 STAGE = np.dtype([('rb0', '<i4'), ('rb1', '<i4'), ('rb', 'u1', 8), ('tb', 'u1', 16), ('sp', '<i4'), ('sq', '<i4'),
                   ('slcm', '<u4'), ('hb_in', 'u1'), ('hj_in', 'u1'), ('hb_out', 'u1'), ('hj_out', 'u1'),
                   ('sgcm', '<u8'), ('prb', 'u1', 8), ('ptb', 'u1', 16)])
-ROUND = np.dtype([('seg', '<i4', KL * 5 + 4)])
+MAXPAIRS = 10  # pair lists for up to 5 register bits
+ROUND = np.dtype([('seg', '<i4', KL * 5 + 4), ('pseg', '<i4', MAXPAIRS + 1)])
+BLK = np.dtype([('m', '<f8', 32), ('mf', '<f4', 32)])
 OP = np.dtype([('pmask', '<u4'), ('lcm_t', '<u4'), ('gcm', '<u8'), ('gtb', '<u8'), ('m0', '<u4'), ('m1', '<u4'),
                ('lt', '<i4'), ('angles', '<i4'), ('m', '<f8', 8), ('theta', '<f8', 2), ('mf', '<f4', 8), ('galt', '<u8'),
                ('amask', '<u4'), ('alt_lcm', '<u4'), ('alt_col', '<u4'), ('alt_rank', '<i4')])
 
 
+def npairs(le):
+    return le * (le - 1) // 2
+
+
+def pair_index(le, ja, jb):
+    return ja * (2 * le - ja - 1) // 2 + (jb - ja - 1)
+
+
 def load_tables(path):
+    """(passes, stages, rounds, ops, two-qubit blocks) as written by tests/sched_dump.cpp."""
     b = open(path, 'rb').read()
-    head = np.frombuffer(b[:64], '<u8')
-    sizes, counts = [int(v) for v in head[:4]], [int(v) for v in head[4:]]
-    assert sizes == [PASS.itemsize, STAGE.itemsize, ROUND.itemsize, OP.itemsize], sizes
-    off, out = 64, []
-    for dt, c in zip((PASS, STAGE, ROUND, OP), counts):
+    head = np.frombuffer(b[:80], '<u8')
+    sizes, counts = [int(v) for v in head[:5]], [int(v) for v in head[5:]]
+    assert sizes == [PASS.itemsize, STAGE.itemsize, ROUND.itemsize, OP.itemsize, BLK.itemsize], sizes
+    off, out = 80, []
+    for dt, c in zip((PASS, STAGE, ROUND, OP, BLK), counts):
         out.append(np.frombuffer(b, dt, c, off).copy())
         off += dt.itemsize * c
-    P, S, RD, O = out
+    P, S, RD, O, B = out
     for o in O:  # factors of angle-defined diagonal ops, as the device fills them in
         if o['angles'] == 1:
             o['m'][0:4] = [1.0, 0.0, np.cos(o['theta'][0]), np.sin(o['theta'][0])]
@@ -47,7 +58,7 @@ def load_tables(path):
             o['m'][0:4] = [1.0, 0.0, np.cos(th), np.sin(th)]
         elif o['angles'] == 2:
             o['m'][0:4] = [np.cos(o['theta'][0]), np.sin(o['theta'][0]), np.cos(o['theta'][1]), np.sin(o['theta'][1])]
-    return P, S, RD, O
+    return P, S, RD, O, B
 
 
 def _layout(st, m, le):
@@ -99,7 +110,17 @@ def _apply_dense(X, op, j, le, et, base, kind, flip_bit):
         X[:, r1] = np.where(lane_ok, n1, a1)
 
 
-def run_schedule(psi, n, m, le, P, S, RD, O):
+def _apply_pair(X, blk, ja, jb, le):
+    """A two-qubit block on register bits ja < jb: each group of four elements times the 4x4."""
+    M = (blk['m'][0::2] + 1j * blk['m'][1::2]).reshape(4, 4)
+    for r0 in range(1 << le):
+        if (r0 >> ja) & 1 or (r0 >> jb) & 1:
+            continue
+        idx = [r0, r0 | (1 << ja), r0 | (1 << jb), r0 | (1 << ja) | (1 << jb)]
+        X[:, idx] = X[:, idx] @ M.T
+
+
+def run_schedule(psi, n, m, le, P, S, RD, O, B):
     psi = psi.copy()
     for ps in P:
         R = [int(v) for v in ps['R'][:m]]
@@ -135,6 +156,12 @@ def run_schedule(psi, n, m, le, P, S, RD, O):
                                     _apply_dense(X, op, j, le, et, base, 'flip', kb)
                                 else:
                                     _apply_dense(X, op, j, le, et, base, 'flip', None)
+                    for ja in range(le):  # two-qubit blocks, after the register-bit lists
+                        for jb in range(ja + 1, le):
+                            pseg = RD[ri]['pseg']
+                            sl = pair_index(le, ja, jb)
+                            for bi in range(pseg[sl], pseg[sl + 1]):
+                                _apply_pair(X, B[bi], ja, jb, le)
                     for oi in range(seg[KL * le], seg[KL * le + 2]):  # sign flips, then other diagonal ops
                         op = O[oi]
                         if (base & int(op['gcm'])) != int(op['gcm']):

@@ -88,10 +88,10 @@ VARIANTS = [(True, 10, 4), (True, 11, 4), (True, 12, 4), (True, 11, 3), (False, 
 @pytest.mark.parametrize("c128,m,le", VARIANTS)
 def test_schedule_reproduces_oracle(dumper, tmp_path, oracle_mod, case, c128, m, le):
     text, n = CASES[case]()
-    P, S, RD, O = tables(dumper, tmp_path, text, n, c128, m, le)
+    P, S, RD, O, B = tables(dumper, tmp_path, text, n, c128, m, le)
     psi0 = wl.gaussian_state(n, 3)
     ref = oracle_mod.run_circuit(text, psi0=psi0)
-    got = sm.run_schedule(psi0, n, m, le, P, S, RD, O)
+    got = sm.run_schedule(psi0, n, m, le, P, S, RD, O, B)
     assert np.max(np.abs(got - ref)) < 1e-12
     sm.check_half_exchanges(P, S, m, le, c128)
     if m - le >= 7:
@@ -102,7 +102,7 @@ def test_brickwork_passes_use_wave_splits(dumper, tmp_path):
     """At 12 resident qubits (complex128, 16 amplitudes per thread) the brickwork's passes take the
     half-size buffer with every split at a wave position."""
     text = wl.brickwork_circuit(16, 8, seed=21)
-    P, S, RD, O = tables(dumper, tmp_path, text, 16, True, 12, 4)
+    P, S, RD, O, B = tables(dumper, tmp_path, text, 16, True, 12, 4)
     nhalf, nwave = sm.check_half_exchanges(P, S, 12, 4, True)
     assert nhalf == len(P) and nwave == len(P)
     assert sm.check_wave_barriers(P, S, 12, 4) == len(P)
@@ -111,7 +111,7 @@ def test_brickwork_passes_use_wave_splits(dumper, tmp_path):
 def test_wave_barrier_model_catches_a_missing_barrier(dumper, tmp_path, monkeypatch):
     """The barrier check fails when one half of a round trip skips a barrier (planted in the model)."""
     text = wl.brickwork_circuit(16, 8, seed=21)
-    P, S, RD, O = tables(dumper, tmp_path, text, 16, True, 12, 4)
+    P, S, RD, O, B = tables(dumper, tmp_path, text, 16, True, 12, 4)
     orig = sm._wave_trace
 
     def drop_one(ps, sts, w):
@@ -129,7 +129,7 @@ def test_wave_barrier_model_catches_an_early_write(dumper, tmp_path, monkeypatch
     """The ordering check fails when the second half writes before its two waiting barriers (the
     barrier count stays equal; planted in the model)."""
     text = wl.brickwork_circuit(16, 8, seed=21)
-    P, S, RD, O = tables(dumper, tmp_path, text, 16, True, 12, 4)
+    P, S, RD, O, B = tables(dumper, tmp_path, text, 16, True, 12, 4)
     orig = sm._wave_trace
 
     def early(ps, sts, w):
