@@ -7,7 +7,7 @@ imports nothing from the product package.
 The update rules live in ``qsim_oracle.c`` (plain loops over the index, one per equation of the
 paper's Sec. III.A). This file parses the circuit text (its own parser), turns each gate name into
 the rule the paper gives for it and calls that rule gate by gate, in file order, with no fusion,
-no reordering and no renormalisation.
+no reordering, and no renormalisation except where the circuit asks for one.
 
 Gate readings (the paper's notation on the left):
   H                      Eq. Hadamard / NUM2                 -> or_hadamard
@@ -20,6 +20,8 @@ Gate readings (the paper's notation on the left):
   Toffoli (TOFFOLI)      Eq. Toffoli / NUM8                  -> or_cnot with two controls
   Pauli X, Y, Z, S, T, RZ, CZ, explicit U: 2x2 matrices applied with the common form of NUM2-NUM8
   (or_unitary); Pauli X uses the flip rule of NUM6 without a control.
+  RENORM                 Eq. STAT1: every amplitude divided by the square root of sum |a_i|^2
+                         (or_norm, FP64); a state whose sum is 0 is left as it is
 """
 from __future__ import annotations
 
@@ -184,6 +186,10 @@ def apply_op(a: np.ndarray, n: int, kw: str, args: list[str]) -> None:
         L.or_cv(p, n, 1 << iv(0), iv(1), fv(2))
     elif kw == "QSWAP":
         L.or_swap(p, n, iv(0), iv(1))
+    elif kw == "RENORM":
+        s = L.or_norm(p, n)
+        if s > 0.0:
+            a /= math.sqrt(s)
     elif kw == "MODEXP":
         xf, xq, ff, fq, y, G = (iv(k) for k in range(6))
         if not (G >= 2 and G <= 2 ** fq and xf + xq <= n and ff + fq <= n and (xf + xq <= ff or ff + fq <= xf)):

@@ -132,13 +132,16 @@ def u_line(q: int, u: np.ndarray) -> str:
     return f"U {q} " + " ".join(vals)
 
 
-def brickwork_circuit(n: int, layers: int = 20, seed: int = 21, layer_range: tuple[int, int] | None = None) -> str:
+def brickwork_circuit(n: int, layers: int = 20, seed: int = 21, layer_range: tuple[int, int] | None = None,
+                      renorm_after: tuple[int, ...] = ()) -> str:
     """Layer l = 0..layers-1: a Haar U on every qubit (qubit order 0..n-1), then CZ(q, q+1) for every
     q = l (mod 2) with q+1 < n. Start |0...0>. layer_range=(a, b) emits only layers a..b-1 (the random
-    draws of all layers are made in the same order, so the pieces concatenate to the full circuit)."""
+    draws of all layers are made in the same order, so the pieces concatenate to the full circuit).
+    renorm_after: a RENORM line after that many layers, once per entry (0: before the first layer)."""
     rng = np.random.default_rng(seed)
     a, b = layer_range if layer_range else (0, layers)
     lines = []
+    lines += ["RENORM"] * sum(1 for k in renorm_after if k == 0)
     for layer in range(layers):
         us = [haar_2x2(rng) for _ in range(n)]
         if not a <= layer < b:
@@ -147,7 +150,9 @@ def brickwork_circuit(n: int, layers: int = 20, seed: int = 21, layer_range: tup
             lines.append(u_line(q, us[q]))
         for q in range(layer % 2, n - 1, 2):
             lines.append(f"CZ {q} {q + 1}")
-    return circuit_text(n, lines, header=[f"brickwork n={n} layers={layers} seed={seed} range={a}..{b - 1}"])
+        lines += ["RENORM"] * sum(1 for k in renorm_after if k == layer + 1)
+    tag = f" renorm_after={','.join(map(str, renorm_after))}" if renorm_after else ""
+    return circuit_text(n, lines, header=[f"brickwork n={n} layers={layers} seed={seed} range={a}..{b - 1}{tag}"])
 
 
 def inverse_lines(text: str) -> list[str]:

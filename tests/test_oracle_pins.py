@@ -466,3 +466,42 @@ def test_qft_sample_closed_forms(oracle_mod):
     u = np.full(N, 1.0 / math.sqrt(N), dtype=np.complex128)
     got = oracle_mod.qft_sample(u, [0, 1, 2, N // 2, N - 1])
     assert abs(got[0] - 1.0) < 1e-13 and np.max(np.abs(got[1:])) < 1e-13
+
+
+# ----------------------------------------------------------------------------------------------
+# Renormalisation points (Eq. STAT1)
+# ----------------------------------------------------------------------------------------------
+def test_renorm_rescales_to_unit_sum(oracle_mod):
+    """RENORM divides every amplitude by the same positive number and leaves sum |a_i|^2 = 1 (Eq.
+    STAT1); the factor is checked against numpy's own 2-norm, not the oracle's sum."""
+    n = 7
+    psi = 3.7 * rand_state(n, 11)
+    out = run(oracle_mod, n, ["RENORM"], psi)
+    r = float(np.linalg.norm(psi))
+    assert abs(float(np.sum(np.abs(out) ** 2)) - 1.0) < 1e-14
+    np.testing.assert_allclose(out * r, psi, rtol=0, atol=1e-13 * r)
+
+
+def test_renorm_special_cases(oracle_mod):
+    n = 5
+    e = np.zeros(2 ** n, dtype=np.complex128)
+    e[9] = 1.0
+    assert np.array_equal(run(oracle_mod, n, ["RENORM"], e), e)  # already normalised: unchanged
+    z = np.zeros(2 ** n, dtype=np.complex128)
+    assert np.array_equal(run(oracle_mod, n, ["RENORM"], z), z)  # sum 0: left as it is
+    neg = -2.0j * e
+    np.testing.assert_allclose(run(oracle_mod, n, ["RENORM"], neg), -1.0j * e, rtol=0, atol=1e-16)  # phase kept
+
+
+def test_renorm_commutes_with_unitary_gates(oracle_mod):
+    """Unitary gates keep sum |a_i|^2, so a RENORM anywhere between them gives the unrenormalised
+    result divided by the initial 2-norm; two RENORMs in a row act as one."""
+    n = 6
+    psi = 0.4 * rand_state(n, 5)
+    gates = ["H 0", "CNOT 0 3", "RX90 2", "CRK 1 4 3", "QSWAP 2 5", "TOFFOLI 0 1 5", "RY90DG 4"]
+    plain = run(oracle_mod, n, gates, psi)
+    r = float(np.linalg.norm(psi))
+    for k in (0, 3, len(gates)):
+        for extra in (["RENORM"], ["RENORM", "RENORM"]):
+            got = run(oracle_mod, n, gates[:k] + extra + gates[k:], psi)
+            np.testing.assert_allclose(got, plain / r, rtol=0, atol=1e-14)
