@@ -419,12 +419,12 @@ def main() -> int:
     renorm = args.renorm_every if args.renorm_every is not None else (10 if dtype == "c64" else 0)
     workload = f"brickwork-{n}q-{dtype}-{args.layers}layers" + (f"-renorm{renorm}" if renorm else "")
     log(f"workload {workload}: generating circuit")
-    # one circuit per group of `renorm` layers (the whole circuit when renorm = 0); the draws of all
-    # layers are made in the same order, so the groups concatenate to the full circuit
-    groups = [(a, min(args.layers, a + renorm)) for a in range(0, args.layers, renorm)] if renorm else [(0, args.layers)]
-    circs = [q.parse_circuit(wl.brickwork_circuit(n, args.layers, args.seed, layer_range=g)) for g in groups]
-    G = sum(len(c.gates) for c in circs)
-    log(f"{G} gates in {len(circs)} group(s); allocating {amp * 2 ** n / 2 ** 30:.0f} GiB state")
+    # one circuit; with renormalisation a RENORM point after every `renorm` layers (the plan folds each
+    # into the passes around it)
+    points = tuple(range(renorm, args.layers + 1, renorm)) if renorm else ()
+    circs = [q.parse_circuit(wl.brickwork_circuit(n, args.layers, args.seed, renorm_after=points))]
+    G = sum(1 for c in circs for g in c.gates if g.op != q._lib.OPS["RENORM"])
+    log(f"{G} gates, {len(points)} renormalisation point(s); allocating {amp * 2 ** n / 2 ** 30:.0f} GiB state")
     state = q.State(n, dtype, device=dev)
     tuned = None
     if args.method == "auto":
@@ -441,14 +441,14 @@ def main() -> int:
         popts = dict(method=args.method, fuse_k=args.fuse_k, lds_qubits=args.lds, lds_regs=args.lds_regs)
     plans = [q.Plan(c, dtype, **popts) for c in circs]
     info = dict(plans[0].info)
-    for k in ("gates", "launches", "passes", "alg_bytes", "alg_flops"):
+    for k in ("gates", "launches", "passes", "alg_bytes", "alg_flops", "issued_flops"):
         info[k] = sum(p.info[k] for p in plans)
+    info["gates"] = G
     log(f"plan {popts}: {info}")
-    norms = []
 
     def run(pl, timed: bool):
-        """One run of the circuit from |0...0>: the first plan generates the initial state (a staged
-        plan inside its first pass), then the groups in order, with FP64 renormalisation after each."""
+        """One run of the circuit from |0...0> (a staged plan generates the initial state inside its
+        first pass), renormalising in FP64 at its RENORM points."""
         ms, kd, fk = [], [], []
         for i, p in enumerate(pl):
             if timed:
@@ -460,15 +460,12 @@ def main() -> int:
                 p.execute_from_zero(state)
             else:
                 p.execute(state)
-            if renorm:
-                norms.append(state.renormalize())
         return (np.concatenate(ms), np.concatenate(kd), np.concatenate(fk)) if timed else None
 
     for i in range(args.warmup):
         run(plans, False)
         torch.cuda.synchronize()
         log(f"warmup {i + 1}/{args.warmup} done")
-    norms.clear()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     launch_ms, kinds, fks = [], None, None
@@ -502,10 +499,12 @@ def main() -> int:
         "roofline": roof,
     }
     if renorm:
-        # FP64 norms just before each renormalisation, last timed step
-        last = norms[-len(plans):]
+        # FP64 squared norms found at the renormalisation points in the last timed step
+        last = [float(x) for p in plans for x in p.norms()]
         out["norm_before_renormalisation"] = last
         out["max_norm_drift"] = max(abs(x - 1.0) for x in last)
+        out["config"]["renormalisation"] = ("folded into the staged passes around each point; a scaling sweep after the "
+                                            "last" if info["method"] == 2 else "a norm sweep and a scaling sweep per point")
 
     # the plain per-gate plan (one sweep per gate) and the fused k = 5 plan (dense 32 x 32 blocks on
     # the matrix cores), each timed whole beside the headline plan
@@ -527,7 +526,7 @@ def main() -> int:
             log(f"{leg} run {r + 1}/{runs}: {walls[-1]:.2f} s in {len(ms)} launches")
         lwall = float(np.mean(walls))
         linfo = dict(lplans[0].info)
-        for k in ("gates", "launches", "passes", "alg_bytes", "alg_flops"):
+        for k in ("gates", "launches", "passes", "alg_bytes", "alg_flops", "issued_flops"):
             linfo[k] = sum(p.info[k] for p in lplans)
         entry = {"gates_per_s": round(G / lwall, 3), "s_per_run": round(lwall, 3), "launches": int(linfo["launches"]),
                  "eff_GBps": round(lbytes / lwall / 1e9, 1), "hbm_frac": round(lbytes / lwall / 1e9 / HBM_PEAK_GBPS, 4),
@@ -579,13 +578,13 @@ def roofline(L, kinds, fks, info, n, dtype, workload) -> dict:
         peak = (FP64_PEAK_TFLOPS if dtype == "c128" else FP32_MFMA_PEAK_TFLOPS) if mfma else \
             (FP64_VALU_PEAK_TFLOPS if dtype == "c128" else FP32_VALU_PEAK_TFLOPS)
     elif kname == "staged":
-        flops = info["alg_flops"] / max(1, info["passes"])
+        flops = info["alg_flops"] / len(idx)  # over the staged passes (not the renormalisation sweeps)
         mfma = False
         peak = FP64_VALU_PEAK_TFLOPS if dtype == "c128" else FP32_VALU_PEAK_TFLOPS
-        # a dense 2x2 with a real first column issues 12 FMAs (24 flops) per pair, against the 28 of the
-        # algorithmic count; complex64 code has no packed FP32 instructions, so it can issue at most
-        # half the published FP32 vector rate
-        issued = {"flops_per_launch": flops * 24.0 / 28.0, "frac_of_peak": None,
+        # the flops the kernels actually issue (the plan's count: 2x2s with a real first column and
+        # two-qubit blocks issue fewer than the algorithmic 14 per amplitude per 2x2); complex64 code has
+        # no packed FP32 instructions, so it can issue at most half the published FP32 vector rate
+        issued = {"flops_per_launch": info["issued_flops"] / len(idx), "frac_of_peak": None,
                   "peak_as_compiled": FP64_VALU_PEAK_TFLOPS if dtype == "c128" else FP32_UNPACKED_PEAK_TFLOPS}
     else:
         flops, mfma, peak = 0.0, False, FP64_VALU_PEAK_TFLOPS

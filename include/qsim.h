@@ -202,6 +202,13 @@ typedef enum {
                            angle is formed from k in FP64 by the library (on the device for plain and
                            staged plans and batches, on the host where gates are fused into matrices) */
     QSIM_OP_RKDG,       /* R(-2 pi / 2^k), the inverse of QSIM_OP_RK */
+    QSIM_OP_RENORM,     /* renormalisation point (plans only; target 0, no controls): the state is rescaled
+                           by 1/sqrt(sum |a_i|^2) so that Eq. STAT1 holds again, the sum formed in FP64
+                           (a state whose sum is 0 is left as it is). A staged plan folds it into its
+                           passes: the pass before the point sums |a|^2 of what it stores, the pass after
+                           it multiplies what it loads; where no pass follows (the point ends the plan)
+                           or none precedes, it runs as a sweep of its own. The squared norms found are
+                           read back with qsim_plan_get_norms */
     QSIM_OP_COUNT_
 } qsim_op;
 
@@ -234,7 +241,8 @@ typedef struct qsim_plan_opts {
 
 typedef struct qsim_plan_info {
     int64_t gates;          /* gates of the original circuit */
-    int64_t launches;       /* kernel launches per execute */
+    int64_t launches;       /* launches per execute (a renormalisation step that is not folded into a
+                               staged pass counts as one: QSIM_KERNEL_RENORM) */
     int64_t passes;         /* launches that read and write the whole state */
     double alg_bytes;       /* algorithmic HBM bytes per execute (per state) */
     double alg_flops;       /* algorithmic flops per execute: 8 * 2^(n+k) per fused k-qubit block;
@@ -245,6 +253,11 @@ typedef struct qsim_plan_info {
     int32_t fuse_k;         /* fused width used (QSIM_PLAN_FUSED) */
     int32_t lds_qubits;     /* resident qubits used (QSIM_PLAN_STAGED) */
     int32_t lds_regs;       /* log2 amplitudes per thread used (QSIM_PLAN_STAGED) */
+    double issued_flops;    /* vector flops the kernels issue per execute (a multiply 1, a multiply-add
+                               2), QSIM_PLAN_STAGED only (0 otherwise): below alg_flops where the plan
+                               applies a 2x2 with a real first column (20 flops per pair) or merges
+                               gates into two-qubit blocks (120 flops per four amplitudes) */
+    int64_t renorms;        /* renormalisation points (QSIM_OP_RENORM) in the gate list */
 } qsim_plan_info;
 
 /* Lower `ngates` gates for states of n qubits and the given dtype. The gate list is copied.
@@ -252,6 +265,12 @@ typedef struct qsim_plan_info {
 int qsim_plan_create(int n, int dtype, const qsim_gate *gates, int64_t ngates, const qsim_plan_opts *opts,
                      qsim_plan **out);
 int qsim_plan_get_info(const qsim_plan *p, qsim_plan_info *info);
+/* The FP64 squared norms sum |a_i|^2 (Eq. STAT1) that the plan's latest execution found at its first
+ * `count` renormalisation points, in gate-list order, each taken just before its rescaling; 0 before
+ * the first execution. Waits for that execution's stream. Executions of one plan on different
+ * streams share these values (and a plan's buffer of per-block partial sums): they must not overlap.
+ * EINVAL if count < 0 or count > info.renorms, or if host_out is NULL with count > 0. */
+int qsim_plan_get_norms(const qsim_plan *p, double *host_out, int64_t count);
 /* Apply the plan to the state (asynchronous on its stream). EINVAL if n or dtype differ. */
 int qsim_plan_execute(qsim_plan *p, qsim_state *s);
 /* Run the plan's circuit from |0...0> (the state's previous contents are ignored): the same result as
@@ -283,7 +302,8 @@ enum {
     QSIM_KERNEL_SWAP = 3,       /* permutation (Eqs. NUM6, NUM8, quantum swap) */
     QSIM_KERNEL_FUSED_VALU = 4, /* dense k <= 3 gate on the vector ALUs */
     QSIM_KERNEL_FUSED_MFMA = 5, /* dense k = 4, 5 gate on the matrix cores */
-    QSIM_KERNEL_STAGED = 6      /* LDS-resident multi-gate pass */
+    QSIM_KERNEL_STAGED = 6,     /* LDS-resident multi-gate pass */
+    QSIM_KERNEL_RENORM = 7      /* renormalisation sweep(s) outside a staged pass (Eq. STAT1) */
 };
 
 /* Kernel forms of an LDS-staged pass, reported by qsim_plan_launches. */
@@ -326,7 +346,7 @@ typedef struct qsim_batch_stats {
  * LDS blocks is split: each of its passes runs as chunks of 4 blocks that any workgroup may take, pass
  * p in launch step p; smaller circuits run whole on one workgroup in step 0. The gate tables, the
  * work lists and the state pool are placed in device memory owned by the batch. EINVAL on malformed
- * input, ENOMEM if the pool does not fit. */
+ * input (a renormalisation point included), ENOMEM if the pool does not fit. */
 int qsim_batch_create(int count, const int *nqubits, const int64_t *offsets, const qsim_gate *gates, int dtype,
                       const qsim_plan_opts *opts, void *stream, qsim_batch **out);
 /* Run every circuit of the batch from |0...0>: one short launch that clears the stamps, then per

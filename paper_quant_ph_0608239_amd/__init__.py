@@ -20,10 +20,12 @@ from .circuit import Circuit, parse_circuit
 
 __all__ = ["State", "Plan", "Batch", "Circuit", "parse_circuit", "QsimError", "lib", "dtype_code",
            "PLAN_PLAIN", "PLAN_FUSED", "PLAN_STAGED", "PLAN_AUTO", "QSIM_C64", "QSIM_C128",
-           "STAGED_FULL", "STAGED_HALF", "STAGED_WAVE", "KERNEL_STAGED", "KERNEL_FUSED_MFMA"]
+           "STAGED_FULL", "STAGED_HALF", "STAGED_WAVE", "KERNEL_STAGED", "KERNEL_FUSED_MFMA",
+           "KERNEL_RENORM"]
 
 KERNEL_STAGED = 6
 KERNEL_FUSED_MFMA = 5
+KERNEL_RENORM = 7
 
 
 def dtype_code(dtype) -> int:
@@ -209,6 +211,13 @@ class Plan:
         """Run the circuit from |0...0> (the state's contents are ignored; a staged plan generates the
         initial state in its first pass)."""
         check(lib().qsim_plan_execute_from_zero(self.handle, state.handle))
+
+    def norms(self) -> np.ndarray:
+        """FP64 squared norms found at the circuit's RENORM points by the latest execution (waits for it)."""
+        R = int(self.info["renorms"])
+        out = np.zeros(max(R, 1), dtype=np.float64)
+        check(lib().qsim_plan_get_norms(self.handle, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), R))
+        return out[:R]
 
     def launches(self):
         """(kind, variant) numpy arrays, one entry per launch, without running the plan: the kernel

@@ -20,12 +20,13 @@ _ERRNAMES = {EINVAL: "EINVAL", ENOMEM: "ENOMEM", EDEVICE: "EDEVICE", EUNSUPPORTE
 OPS = {
     "MATRIX": 0, "H": 1, "X": 2, "Y": 3, "Z": 4, "S": 5, "SDG": 6, "T": 7, "TDG": 8,
     "RX90": 9, "RX90DG": 10, "RY90": 11, "RY90DG": 12, "PHASE": 13, "RZ": 14, "V": 15, "SWAP": 16,
-    "RK": 17, "RKDG": 18,
+    "RK": 17, "RKDG": 18, "RENORM": 19,
 }
 
 PLAN_PLAIN, PLAN_FUSED, PLAN_STAGED, PLAN_AUTO = 0, 1, 2, 3
 STAGED_FULL, STAGED_HALF, STAGED_WAVE = 0, 1, 2
-KERNEL_NAMES = {0: "general", 1: "phase", 2: "diag", 3: "swap", 4: "fused_valu", 5: "fused_mfma", 6: "staged"}
+KERNEL_NAMES = {0: "general", 1: "phase", 2: "diag", 3: "swap", 4: "fused_valu", 5: "fused_mfma", 6: "staged",
+                7: "renorm"}
 
 
 class QsimError(RuntimeError):
@@ -50,7 +51,8 @@ class PlanOpts(ctypes.Structure):
 class PlanInfo(ctypes.Structure):
     _fields_ = [("gates", ctypes.c_int64), ("launches", ctypes.c_int64), ("passes", ctypes.c_int64),
                 ("alg_bytes", ctypes.c_double), ("alg_flops", ctypes.c_double), ("method", ctypes.c_int32),
-                ("fuse_k", ctypes.c_int32), ("lds_qubits", ctypes.c_int32), ("lds_regs", ctypes.c_int32)]
+                ("fuse_k", ctypes.c_int32), ("lds_qubits", ctypes.c_int32), ("lds_regs", ctypes.c_int32),
+                ("issued_flops", ctypes.c_double), ("renorms", ctypes.c_int64)]
 
 
 class BatchStats(ctypes.Structure):
@@ -99,6 +101,7 @@ SIGNATURES = {
     "qsim_sample": (_i32, [_vp, _i64, _dp, ctypes.POINTER(_u64)]),
     "qsim_plan_create": (_i32, [_i32, _i32, ctypes.POINTER(Gate), _i64, ctypes.POINTER(PlanOpts), ctypes.POINTER(_vp)]),
     "qsim_plan_get_info": (_i32, [_vp, ctypes.POINTER(PlanInfo)]),
+    "qsim_plan_get_norms": (_i32, [_vp, _dp, _i64]),
     "qsim_plan_execute": (_i32, [_vp, _vp]),
     "qsim_plan_free": (_i32, [_vp]),
     "qsim_plan_launches": (_i32, [_vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]),

@@ -90,6 +90,8 @@ def parse_circuit(text: str) -> Circuit:
             g = _gate("X", int(a[2]), controls=(1 << int(a[0])) | (1 << int(a[1])))
         elif kw == "QSWAP":
             g = _gate("SWAP", int(a[0]), target2=int(a[1]))
+        elif kw == "RENORM":
+            g = _gate("RENORM", 0)
         else:
             raise ValueError(f"unknown gate keyword {kw!r}")
         gates.append(g)

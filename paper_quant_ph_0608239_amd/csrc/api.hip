@@ -126,6 +126,8 @@ int gate_matrix(const qsim_gate &g, double u[8])
 int validate_gate(const qsim_gate &g, int n)
 {
     if (g.op < 0 || g.op >= QSIM_OP_COUNT_) return set_error(QSIM_EINVAL, "gate: unknown op code");
+    if (g.op == QSIM_OP_RENORM && (g.target != 0 || g.controls != 0))
+        return set_error(QSIM_EINVAL, "gate: a renormalisation point takes no qubits (target 0, no controls)");
     if (g.target < 0 || g.target >= n) return set_error(QSIM_EINVAL, "gate: target out of range");
     if (n < 64 && (g.controls >> n) != 0) return set_error(QSIM_EINVAL, "gate: control mask has bits >= n");
     if ((g.controls >> g.target) & 1) return set_error(QSIM_EINVAL, "gate: control mask contains the target");
@@ -144,6 +146,7 @@ int validate_gate(const qsim_gate &g, int n)
 // one gate record as one sweep (the per-gate path); phase angles are evaluated on the device
 int apply_gate_record(qsim_state *s, const qsim_gate &g)
 {
+    if (g.op == QSIM_OP_RENORM) return set_error(QSIM_EINVAL, "a renormalisation point runs only inside a plan");
     const uint64_t tbit = uint64_t(1) << g.target;
     if (g.op == QSIM_OP_SWAP) {
         const uint64_t b2 = uint64_t(1) << g.target2;

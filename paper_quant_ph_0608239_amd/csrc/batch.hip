@@ -54,13 +54,13 @@ __device__ __forceinline__ void item_block(T *__restrict__ a, const SPass &pass,
                                            bool init)
 {
     if constexpr (FORM == kWave) {
-        run_block_wave<T, LOG_E, LOG_T>(a, pass, b, stages, rounds, ops, blks, lds, init);
+        run_block_wave<T, LOG_E, LOG_T>(a, pass, b, stages, rounds, ops, blks, lds, init, SEdge{nullptr, nullptr});
         __syncthreads();
     } else if constexpr (FORM == kHalf) {
-        run_block_half<T, LOG_E, LOG_T>(a, pass, b, stages, rounds, ops, blks, lds, init);
+        run_block_half<T, LOG_E, LOG_T>(a, pass, b, stages, rounds, ops, blks, lds, init, SEdge{nullptr, nullptr});
         __syncthreads();
     } else {
-        run_block<T, LOG_E, LOG_T>(a, pass, b, stages, rounds, ops, blks, lds, init);  // ends with a barrier
+        run_block<T, LOG_E, LOG_T>(a, pass, b, stages, rounds, ops, blks, lds, init, SEdge{nullptr, nullptr});  // ends with a barrier
     }
 }
 
@@ -272,11 +272,16 @@ int qsim_batch_create(int count, const int *nqubits, const int64_t *offsets, con
         bc.n = nqubits[c];
         bc.n_eff = std::max(bc.n, m);
         std::vector<qsim_gate> gl(gates + offsets[c], gates + offsets[c + 1]);
-        for (const qsim_gate &g : gl)
+        for (const qsim_gate &g : gl) {
             if (int rc = validate_gate(g, bc.n)) {
                 delete b;
                 return rc;
             }
+            if (g.op == QSIM_OP_RENORM) {
+                delete b;
+                return set_error(QSIM_EINVAL, "batch: renormalisation points run only inside plans");
+            }
+        }
         b->total_gates += int64_t(gl.size());
         bc.pass_begin = int(passes.size());
         if (int rc = staged_schedule(bc.n_eff, dtype, m, log_e, gl, passes, stages, rounds, ops, blks)) {

@@ -31,7 +31,8 @@ int staged_build(int n, int dtype, const std::vector<qsim_gate> &gates, int lds_
 int staged_execute(StagedPlan *p, qsim_state *s, bool from_zero);
 int staged_execute_timed(StagedPlan *p, qsim_state *s, bool from_zero, double *ms, int32_t *kind, int32_t *fk);
 void staged_free(StagedPlan *p);
-void staged_launch_variants(const StagedPlan *p, int32_t *variant);
+void staged_launch_list(const StagedPlan *p, int32_t *kind, int32_t *variant);
+double *staged_norms(StagedPlan *p);
 
 }  // namespace qsim
 
@@ -42,7 +43,7 @@ namespace {
 std::atomic<uint64_t> g_plan_ids{1};
 
 struct Step {
-    int type = 0;  // 0 = single gate, 1 = fused
+    int type = 0;  // 0 = single gate, 1 = fused, 2 = renormalisation point number k
     qsim_gate g{};
     int k = 0;
     int qubits[5] = {0, 0, 0, 0, 0};
@@ -136,6 +137,10 @@ struct qsim_plan {
     std::vector<Step> steps;
     void *dev_w = nullptr;  // device W table for fused k >= 4
     StagedPlan *staged = nullptr;
+    // plain and fused plans with renormalisation points: [0, renorms) squared norms, then kAuxLevel2
+    // partial sums
+    double *d_aux = nullptr;
+    hipStream_t last_stream = nullptr;  // stream of the latest execution
 };
 
 namespace qsim {
@@ -154,7 +159,10 @@ static int build_fused(qsim_plan *p, const std::vector<qsim_gate> &gates, int km
     const size_t G = gates.size();
     std::vector<unsigned char> wtable;
     std::vector<uint64_t> gq(G);
-    for (size_t i = 0; i < G; ++i) gq[i] = gate_qubits(gates[i]);
+    // a renormalisation point depends on every gate before it and every gate after it depends on it;
+    // it is never absorbed into a block (its qubit set is wider than any block)
+    for (size_t i = 0; i < G; ++i) gq[i] = gates[i].op == QSIM_OP_RENORM ? ~uint64_t(0) : gate_qubits(gates[i]);
+    int renorm_no = 0;
     // per-qubit ordered gate lists and front pointers
     std::vector<std::vector<uint32_t>> onq(64);
     for (size_t i = 0; i < G; ++i)
@@ -181,6 +189,14 @@ static int build_fused(qsim_plan *p, const std::vector<qsim_gate> &gates, int km
         std::vector<size_t> members{g0};
         uint64_t Q = gq[g0];
         place(g0);
+        if (gates[g0].op == QSIM_OP_RENORM) {
+            Step st;
+            st.type = 2;
+            st.k = renorm_no++;
+            p->steps.push_back(st);
+            p->info.alg_bytes += 3.0 * std::ldexp(1.0, n) * amp_bytes(p->dtype);  // norm read, scale read and write
+            continue;
+        }
         if (__builtin_popcountll(Q) <= kmax) {
             bool grew = true;
             while (grew) {
@@ -257,8 +273,11 @@ static int build_fused(qsim_plan *p, const std::vector<qsim_gate> &gates, int km
     return QSIM_OK;
 }
 
+static size_t aux_l2_offset(const qsim_plan *p) { return (size_t(p->info.renorms) + 31) / 32 * 32; }
+
 static int kernel_kind(const Step &st)
 {
+    if (st.type == 2) return QSIM_KERNEL_RENORM;
     if (st.type == 1) return st.k >= 4 ? QSIM_KERNEL_FUSED_MFMA : QSIM_KERNEL_FUSED_VALU;
     const qsim_gate &g = st.g;
     if (g.op == QSIM_OP_SWAP) return QSIM_KERNEL_SWAP;
@@ -276,6 +295,11 @@ static int kernel_kind(const Step &st)
 
 static int run_step(qsim_plan *p, qsim_state *s, const Step &st)
 {
+    if (st.type == 2) {
+        double *nrm = p->d_aux + st.k;
+        if (int rc = launch_norm_into(s, p->d_aux + aux_l2_offset(p), nrm)) return rc;
+        return launch_renorm_scale(s, nrm);
+    }
     if (st.type == 0) return apply_gate_record(s, st.g);
     if (st.k >= 4) return launch_fused_mfma(s, st.k, st.qubits, static_cast<unsigned char *>(p->dev_w) + st.wofs);
     return launch_fused_valu(s, st.k, st.qubits, st.U.data());
@@ -314,16 +338,8 @@ static int run_steps(qsim_plan *p, qsim_state *s, bool from_zero = false)
     if (p->staged) return staged_execute(p->staged, s, from_zero);
     if (from_zero)
         if (int rc = launch_set_basis(s, 0)) return rc;
-    for (const Step &st : p->steps) {
-        int rc;
-        if (st.type == 0)
-            rc = apply_gate_record(s, st.g);
-        else if (st.k >= 4)
-            rc = launch_fused_mfma(s, st.k, st.qubits, static_cast<unsigned char *>(p->dev_w) + st.wofs);
-        else
-            rc = launch_fused_valu(s, st.k, st.qubits, st.U.data());
-        if (rc) return rc;
-    }
+    for (const Step &st : p->steps)
+        if (int rc = run_step(p, s, st)) return rc;
     return QSIM_OK;
 }
 
@@ -356,10 +372,19 @@ int qsim_plan_create(int n, int dtype, const qsim_gate *gates, int64_t ngates, c
     p->opts = o;
     p->info.gates = ngates;
     p->info.method = o.method;
+    for (const qsim_gate &g : gl) p->info.renorms += g.op == QSIM_OP_RENORM;
     int rc = QSIM_OK;
     if (o.method == QSIM_PLAN_PLAIN) {
+        int renorm_no = 0;
         for (const qsim_gate &g : gl) {
             Step st;
+            if (g.op == QSIM_OP_RENORM) {
+                st.type = 2;
+                st.k = renorm_no++;
+                p->steps.push_back(st);
+                p->info.alg_bytes += 3.0 * std::ldexp(1.0, n) * amp_bytes(dtype);  // norm read, scale read and write
+                continue;
+            }
             st.g = g;
             p->steps.push_back(st);
             p->info.alg_bytes += 2.0 * touched(g, n) * amp_bytes(dtype);
@@ -370,7 +395,14 @@ int qsim_plan_create(int n, int dtype, const qsim_gate *gates, int64_t ngates, c
     } else {
         rc = staged_build(n, dtype, gl, o.lds_qubits, o.lds_regs, &p->staged, &p->info);
         if (rc == QSIM_OK)
-            for (const qsim_gate &g : gl) p->info.alg_flops += valu_flops(g, n);
+            for (const qsim_gate &g : gl)
+                if (g.op != QSIM_OP_RENORM) p->info.alg_flops += valu_flops(g, n);
+    }
+    if (rc == QSIM_OK && !p->staged && p->info.renorms > 0) {
+        const size_t words = aux_l2_offset(p) + kAuxLevel2;
+        hipError_t e = hipMalloc(&p->d_aux, sizeof(double) * words);
+        if (e == hipSuccess) e = hipMemset(p->d_aux, 0, sizeof(double) * words);
+        if (e != hipSuccess) rc = hip_error(e, "plan renormalisation buffer");
     }
     if (rc) {
         qsim_plan_free(p);
@@ -379,7 +411,8 @@ int qsim_plan_create(int n, int dtype, const qsim_gate *gates, int64_t ngates, c
     if (!p->staged) {
         p->info.launches = int64_t(p->steps.size());
         int64_t passes = 0;
-        for (const Step &st : p->steps) passes += (st.type == 1) || touched(st.g, n) >= std::ldexp(1.0, n);
+        for (const Step &st : p->steps)
+            passes += st.type != 0 || touched(st.g, n) >= std::ldexp(1.0, n);  // a renormalisation step rescales the whole state
         p->info.passes = passes;
     }
     *out = p;
@@ -397,6 +430,7 @@ int qsim_plan_execute(qsim_plan *p, qsim_state *s)
 {
     if (!p || !s || !s->data) return set_error(QSIM_EINVAL, "null argument");
     if (p->n != s->n || p->dtype != s->dtype) return set_error(QSIM_EINVAL, "plan and state differ in n or dtype");
+    p->last_stream = s->stream;
     if (!p->opts.use_graph || s->stream == nullptr) return run_steps(p, s);
     if (s->graph_exec && s->graph_plan == reinterpret_cast<const void *>(p->id)) {
         QSIM_HIP(hipGraphLaunch(s->graph_exec, s->stream));
@@ -436,8 +470,7 @@ int qsim_plan_launches(const qsim_plan *p, int32_t *kind, int32_t *variant)
 {
     if (!p) return set_error(QSIM_EINVAL, "null argument");
     if (p->staged) {
-        for (int64_t i = 0; kind && i < p->info.launches; ++i) kind[i] = QSIM_KERNEL_STAGED;
-        if (variant) staged_launch_variants(p->staged, variant);
+        staged_launch_list(p->staged, kind, variant);
         return QSIM_OK;
     }
     for (size_t i = 0; i < p->steps.size(); ++i) {
@@ -451,7 +484,20 @@ int qsim_plan_execute_from_zero(qsim_plan *p, qsim_state *s)
 {
     if (!p || !s || !s->data) return set_error(QSIM_EINVAL, "null argument");
     if (p->n != s->n || p->dtype != s->dtype) return set_error(QSIM_EINVAL, "plan and state differ in n or dtype");
+    p->last_stream = s->stream;
     return run_steps(p, s, true);
+}
+
+int qsim_plan_get_norms(const qsim_plan *p, double *host_out, int64_t count)
+{
+    if (!p) return set_error(QSIM_EINVAL, "null argument");
+    if (count < 0 || count > p->info.renorms) return set_error(QSIM_EINVAL, "get_norms: count outside 0..renorms");
+    if (count == 0) return QSIM_OK;
+    if (!host_out) return set_error(QSIM_EINVAL, "get_norms: host_out is NULL");
+    const double *src = p->staged ? staged_norms(p->staged) : p->d_aux;
+    QSIM_HIP(hipMemcpyAsync(host_out, src, sizeof(double) * size_t(count), hipMemcpyDeviceToHost, p->last_stream));
+    QSIM_HIP(hipStreamSynchronize(p->last_stream));
+    return QSIM_OK;
 }
 
 int qsim_plan_execute_timed(qsim_plan *p, qsim_state *s, int from_zero, double *launch_ms, int32_t *kind,
@@ -459,6 +505,7 @@ int qsim_plan_execute_timed(qsim_plan *p, qsim_state *s, int from_zero, double *
 {
     if (!p || !s || !s->data) return set_error(QSIM_EINVAL, "null argument");
     if (p->n != s->n || p->dtype != s->dtype) return set_error(QSIM_EINVAL, "plan and state differ in n or dtype");
+    p->last_stream = s->stream;
     return run_steps_timed(p, s, from_zero != 0, launch_ms, kind, fused_k);
 }
 
@@ -473,8 +520,9 @@ int qsim_plan_tune(int n, int dtype, const qsim_gate *gates, int64_t ngates, qsi
     if (include_plain) cand.push_back(qsim_plan_opts{QSIM_PLAN_PLAIN, 0, 0, 0, 0});
     for (int k = 2; k <= 5; ++k) cand.push_back(qsim_plan_opts{QSIM_PLAN_FUSED, k, 0, 0, 0});
     // (resident qubits, log2 amplitudes per thread) of the compiled LDS-staged variants
-    // (13 resident qubits for complex128 and 14 for complex64 leave room for one workgroup per CU;
-    // they measured slower than two smaller ones on the brickwork and are not candidates)
+    // (13 resident qubits for complex128 and 14 for complex64 leave room for one workgroup per CU, or two
+    // of 512 threads in the wave-split form; both measured 40% slower than the smaller blocks on the
+    // brickwork and are not candidates)
     static const int v128[][2] = {{12, 4}, {11, 4}, {10, 4}, {12, 3}, {11, 3}, {10, 3}};
     static const int v64[][2] = {{12, 4}, {11, 4}, {13, 4}, {13, 5}, {12, 5}, {11, 5}};
     for (const auto &v : dtype == QSIM_C128 ? v128 : v64)
@@ -546,6 +594,7 @@ int qsim_plan_free(qsim_plan *p)
 {
     if (!p) return QSIM_OK;
     if (p->dev_w) hipFree(p->dev_w);
+    if (p->d_aux) hipFree(p->d_aux);
     if (p->staged) staged_free(p->staged);
     delete p;
     return QSIM_OK;

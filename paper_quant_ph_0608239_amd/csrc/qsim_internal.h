@@ -133,6 +133,15 @@ int run_norm(qsim_state *s, double *host_out);
 int launch_probs(qsim_state *s, double *dev_out, uint64_t first, uint64_t count);
 int run_marginals(qsim_state *s, double *host_out);
 int launch_scale(qsim_state *s, const double *dev_factor);
+// Renormalisation steps of plans (Eq. STAT1), asynchronous on the state's stream. launch_norm_into:
+// *out = FP64 sum of |a|^2 over the state, through `partial` (kAuxLevel2 doubles). launch_renorm_scale:
+// the state times 1/sqrt(*norm), unchanged when *norm is not positive. launch_sum_array: *out = the sum
+// of x[0..count) in a fixed order, through `level2` (kAuxLevel2 doubles).
+constexpr int kReduceMaxGrid = 4096;
+constexpr int kAuxLevel2 = 4096;
+int launch_norm_into(qsim_state *s, double *partial, double *out);
+int launch_renorm_scale(qsim_state *s, const double *norm);
+int launch_sum_array(const double *x, uint64_t count, double *level2, double *out, hipStream_t stream);
 int run_renormalize(qsim_state *s, double *norm_before);
 int run_sample(qsim_state *s, int64_t shots, const double *uniforms, uint64_t *out);
 

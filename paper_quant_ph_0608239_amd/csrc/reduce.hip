@@ -83,6 +83,16 @@ __global__ __launch_bounds__(kBlock) void k_sum_final(const double *__restrict__
     }
 }
 
+// grid-stride partial sums of an FP64 array (the per-block partials of a pass that accumulated the norm)
+__global__ __launch_bounds__(kBlock) void k_sum_partial(const double *__restrict__ x, uint64_t count, double *__restrict__ partial)
+{
+    __shared__ double lds[kWaves];
+    double acc = 0.0;
+    for (uint64_t i = uint64_t(blockIdx.x) * kBlock + threadIdx.x; i < count; i += uint64_t(gridDim.x) * kBlock) acc += x[i];
+    const double r = block_sum(acc, lds);
+    if (threadIdx.x == 0) partial[blockIdx.x] = r;
+}
+
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_probs(const T *__restrict__ a, double *__restrict__ p, uint64_t first,
                                                  uint64_t count)
@@ -232,17 +242,18 @@ inline unsigned reduce_grid(uint64_t items)
 {
     uint64_t g = (items + kBlock * 8 - 1) / (kBlock * 8);
     if (g < 1) g = 1;
-    if (g > 4096) g = 4096;
+    if (g > kReduceMaxGrid) g = kReduceMaxGrid;
     return unsigned(g);
 }
 
 }  // namespace
 
-static int norm_to_scratch(qsim_state *s)
+static_assert(kReduceMaxGrid <= kAuxLevel2, "a level-2 buffer holds one partial per reduction workgroup");
+
+int launch_norm_into(qsim_state *s, double *partial, double *out)
 {
     const uint64_t N = dim(s->n);
     const unsigned g = reduce_grid(s->dtype == QSIM_C128 ? N : N / 2 + 1);
-    double *partial = s->scratch + 8;
     if (s->dtype == QSIM_C128)
         hipLaunchKernelGGL(k_norm_partial<double>, dim3(g), dim3(kBlock), 0, s->stream, static_cast<const double *>(s->data), N,
                            partial);
@@ -250,7 +261,33 @@ static int norm_to_scratch(qsim_state *s)
         hipLaunchKernelGGL(k_norm_partial<float>, dim3(g), dim3(kBlock), 0, s->stream, static_cast<const float *>(s->data), N,
                            partial);
     QSIM_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(kBlock), 0, s->stream, partial, int(g), 1, 1, s->scratch);
+    hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(kBlock), 0, s->stream, partial, int(g), 1, 1, out);
+    QSIM_HIP(hipGetLastError());
+    return QSIM_OK;
+}
+
+static int norm_to_scratch(qsim_state *s) { return launch_norm_into(s, s->scratch + 8, s->scratch); }
+
+int launch_sum_array(const double *x, uint64_t count, double *level2, double *out, hipStream_t stream)
+{
+    const unsigned g = reduce_grid(count);
+    hipLaunchKernelGGL(k_sum_partial, dim3(g), dim3(kBlock), 0, stream, x, count, level2);
+    QSIM_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(kBlock), 0, stream, level2, int(g), 1, 1, out);
+    QSIM_HIP(hipGetLastError());
+    return QSIM_OK;
+}
+
+int launch_renorm_scale(qsim_state *s, const double *norm)
+{
+    const uint64_t N = dim(s->n);
+    const unsigned g = reduce_grid(N);
+    if (s->dtype == QSIM_C128)
+        hipLaunchKernelGGL(k_scale<double>, dim3(g), dim3(kBlock), 0, s->stream, static_cast<double *>(s->data), N, norm, 2,
+                           nullptr);
+    else
+        hipLaunchKernelGGL(k_scale<float>, dim3(g), dim3(kBlock), 0, s->stream, static_cast<float *>(s->data), N, norm, 2,
+                           nullptr);
     QSIM_HIP(hipGetLastError());
     return QSIM_OK;
 }

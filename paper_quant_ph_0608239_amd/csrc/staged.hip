@@ -37,49 +37,49 @@ namespace {
 // persistent grid that prefetches each workgroup's next block into registers while the current one
 // is processed measured slower on gfx950: the extra registers and the wait for the previous block's
 // stores cost more than the overlap gained.)
-template <typename T, int LOG_E, int LOG_T, int MINW>
+template <typename T, int LOG_E, int LOG_T, int MINW, bool EDGE>
 __global__ __launch_bounds__(1 << LOG_T, MINW) void k_staged(T *__restrict__ a, const SPass *__restrict__ passp,
                                                              const SStage *__restrict__ stages, const SRound *__restrict__ rounds,
                                                              const SOp *__restrict__ ops, const SBlk *__restrict__ blks,
-                                                             int init_zero)
+                                                             int init_zero, const double *scale, double *norm)
 {
     using C = typename Vec<T>::C;
     __shared__ C lds[lds_slots<T>(LOG_E + LOG_T)];
     const SPass pass = ldc<SPass>(as_const(passp));
-    run_block<T, LOG_E, LOG_T>(a, pass, blockIdx.x, as_const(stages), as_const(rounds), as_const(ops), as_const(blks), lds,
-                               init_zero != 0);
+    run_block<T, LOG_E, LOG_T, EDGE>(a, pass, blockIdx.x, as_const(stages), as_const(rounds), as_const(ops), as_const(blks), lds,
+                               init_zero != 0, SEdge{scale, norm});
 }
 
 // The same pass with a buffer of half the block (every LDS round trip in two halves): twice the
 // workgroups per CU where LDS, not registers, bounds the occupancy.
-template <typename T, int LOG_E, int LOG_T, int MINW>
+template <typename T, int LOG_E, int LOG_T, int MINW, bool EDGE>
 __global__ __launch_bounds__(1 << LOG_T, MINW) void k_staged_half(T *__restrict__ a, const SPass *__restrict__ passp,
                                                                   const SStage *__restrict__ stages,
                                                                   const SRound *__restrict__ rounds,
                                                                   const SOp *__restrict__ ops, const SBlk *__restrict__ blks,
-                                                                  int init_zero)
+                                                                  int init_zero, const double *scale, double *norm)
 {
     using C = typename Vec<T>::C;
     __shared__ C lds[lds_slots<T>(LOG_E + LOG_T - 1)];
     const SPass pass = ldc<SPass>(as_const(passp));
-    run_block_half<T, LOG_E, LOG_T>(a, pass, blockIdx.x, as_const(stages), as_const(rounds), as_const(ops), as_const(blks), lds,
-                                    init_zero != 0);
+    run_block_half<T, LOG_E, LOG_T, EDGE>(a, pass, blockIdx.x, as_const(stages), as_const(rounds), as_const(ops), as_const(blks), lds,
+                                    init_zero != 0, SEdge{scale, norm});
 }
 
 // The half-buffer pass when every split is at a wave position: uniform split branches, and the block
 // fits in 128 VGPRs, so four 256-thread workgroups share a CU.
-template <typename T, int LOG_E, int LOG_T, int MINW>
+template <typename T, int LOG_E, int LOG_T, int MINW, bool EDGE>
 __global__ __launch_bounds__(1 << LOG_T, MINW) void k_staged_wave(T *__restrict__ a, const SPass *__restrict__ passp,
                                                                   const SStage *__restrict__ stages,
                                                                   const SRound *__restrict__ rounds,
                                                                   const SOp *__restrict__ ops, const SBlk *__restrict__ blks,
-                                                                  int init_zero)
+                                                                  int init_zero, const double *scale, double *norm)
 {
     using C = typename Vec<T>::C;
     __shared__ C lds[lds_slots<T>(LOG_E + LOG_T - 1)];
     const SPass pass = ldc<SPass>(as_const(passp));
-    run_block_wave<T, LOG_E, LOG_T>(a, pass, blockIdx.x, as_const(stages), as_const(rounds), as_const(ops), as_const(blks), lds,
-                                    init_zero != 0);
+    run_block_wave<T, LOG_E, LOG_T, EDGE>(a, pass, blockIdx.x, as_const(stages), as_const(rounds), as_const(ops), as_const(blks), lds,
+                                    init_zero != 0, SEdge{scale, norm});
 }
 
 }  // namespace
@@ -112,14 +112,30 @@ __global__ void k_op_angles(SOp *ops, int nops)
 struct StagedPlan;
 void staged_free(StagedPlan *p);
 
+// One launch of a staged plan: a pass, or a renormalisation sweep that no pass can take.
+enum { kActPass = 0, kActNorm = 1, kActScale = 2 };
+struct StagedAct {
+    int type;
+    int index;  // the pass, or the renormalisation point whose squared norm the sweep writes or applies
+};
+
 struct StagedPlan {
     int n = 0, dtype = 0, m = 0, log_e = 0, log_t = 0;
     std::vector<SPass> passes;
+    // renormalisation points folded into the passes: per pass, the point whose squared norm scales its
+    // loads and the point its stores' norm goes to (-1: none)
+    std::vector<int> scale_of, norm_of;
+    std::vector<StagedAct> acts;  // launch order
+    int renorms = 0;
     SPass *d_passes = nullptr;
     SStage *d_stages = nullptr;
     SRound *d_rounds = nullptr;
     SOp *d_ops = nullptr;
     SBlk *d_blks = nullptr;
+    // renormalisation buffer: [0, renorms) squared norms, then kAuxLevel2 level-2 partial sums at
+    // aux_l2, then one partial sum per block at aux_part
+    double *d_aux = nullptr;
+    size_t aux_l2 = 0, aux_part = 0;
 };
 
 namespace {
@@ -1120,7 +1136,21 @@ int staged_build(int n, int dtype, const std::vector<qsim_gate> &gates, int lds_
     std::vector<SRound> rounds;
     std::vector<SOp> ops;
     std::vector<SBlk> blks;
-    if (int rc = staged_schedule(n, dtype, m, log_e, gates, passes, stages, rounds, ops, blks)) return rc;
+    // renormalisation points cut the gate list into segments, each scheduled on its own (a point is a
+    // pass boundary); the segments' passes follow each other in the tables
+    std::vector<std::vector<qsim_gate>> segs(1);
+    for (const qsim_gate &g : gates) {
+        if (g.op == QSIM_OP_RENORM) segs.emplace_back();
+        else segs.back().push_back(g);
+    }
+    const int R = int(segs.size()) - 1;
+    std::vector<int> seg_first(segs.size()), seg_end(segs.size());
+    for (size_t k = 0; k < segs.size(); ++k) {
+        seg_first[k] = int(passes.size());
+        if (!segs[k].empty())
+            if (int rc = staged_schedule(n, dtype, m, log_e, segs[k], passes, stages, rounds, ops, blks)) return rc;
+        seg_end[k] = int(passes.size());
+    }
     StagedPlan *p = new StagedPlan();
     p->n = n;
     p->dtype = dtype;
@@ -1128,14 +1158,48 @@ int staged_build(int n, int dtype, const std::vector<qsim_gate> &gates, int lds_
     p->log_e = log_e;
     p->log_t = log_t;
     p->passes = passes;
+    p->renorms = R;
+    // Launch order. Point k takes its norm from the last pass of the segment before it and gives its
+    // factor to the first pass of the segment after it; an empty segment before it means a norm sweep
+    // (after any factor still owed), and a point with no pass after it ends in a scaling sweep.
+    p->scale_of.assign(passes.size(), -1);
+    p->norm_of.assign(passes.size(), -1);
+    int owed = -1;  // the point whose factor the state has not received yet
+    bool norm_in_pass = false;
+    for (size_t k = 0; k < segs.size(); ++k) {
+        const bool point_after = int(k) < R;
+        if (seg_end[k] > seg_first[k]) {
+            if (owed >= 0) p->scale_of[size_t(seg_first[k])] = owed;
+            owed = -1;
+            for (int i = seg_first[k]; i < seg_end[k]; ++i) p->acts.push_back(StagedAct{kActPass, i});
+            if (point_after) {
+                p->norm_of[size_t(seg_end[k] - 1)] = int(k);
+                norm_in_pass = true;
+                owed = int(k);
+            }
+        } else if (point_after) {
+            if (owed >= 0) p->acts.push_back(StagedAct{kActScale, owed});
+            p->acts.push_back(StagedAct{kActNorm, int(k)});
+            owed = int(k);
+        }
+    }
+    if (owed >= 0) p->acts.push_back(StagedAct{kActScale, owed});
     // one device copy of each pass record, of the stage table and of the op table
-    hipError_t e = hipMalloc(&p->d_passes, sizeof(SPass) * passes.size());
+    hipError_t e = hipMalloc(&p->d_passes, sizeof(SPass) * std::max<size_t>(1, passes.size()));
+    if (e == hipSuccess && R > 0) {
+        p->aux_l2 = (size_t(R) + 31) / 32 * 32;
+        p->aux_part = p->aux_l2 + kAuxLevel2;
+        const size_t words = p->aux_part + (norm_in_pass ? size_t(dim(n - m)) : 0);
+        e = hipMalloc(&p->d_aux, sizeof(double) * words);
+        if (e == hipSuccess) e = hipMemset(p->d_aux, 0, sizeof(double) * words);
+    }
     if (e == hipSuccess) e = hipMalloc(&p->d_stages, sizeof(SStage) * std::max<size_t>(1, stages.size()));
     if (e == hipSuccess) e = hipMalloc(&p->d_rounds, sizeof(SRound) * std::max<size_t>(1, rounds.size()));
     if (e == hipSuccess) e = hipMalloc(&p->d_ops, sizeof(SOp) * std::max<size_t>(1, ops.size()));
     if (e == hipSuccess) e = hipMalloc(&p->d_blks, sizeof(SBlk) * std::max<size_t>(1, blks.size()));
     if (e == hipSuccess && !blks.empty()) e = hipMemcpy(p->d_blks, blks.data(), sizeof(SBlk) * blks.size(), hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(p->d_passes, passes.data(), sizeof(SPass) * passes.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess && !passes.empty())
+        e = hipMemcpy(p->d_passes, passes.data(), sizeof(SPass) * passes.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess && !stages.empty())
         e = hipMemcpy(p->d_stages, stages.data(), sizeof(SStage) * stages.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess && !rounds.empty())
@@ -1153,33 +1217,76 @@ int staged_build(int n, int dtype, const std::vector<qsim_gate> &gates, int lds_
     info->method = QSIM_PLAN_STAGED;
     info->lds_qubits = m;
     info->lds_regs = log_e;
-    info->launches = int64_t(passes.size());
-    info->passes = int64_t(passes.size());
-    info->alg_bytes = double(passes.size()) * 2.0 * std::ldexp(1.0, n) * amp_bytes(dtype);
+    // a norm sweep reads the state once, a scaling sweep reads and writes it
+    int64_t norm_sweeps = 0, scale_sweeps = 0;
+    for (const StagedAct &a : p->acts) {
+        norm_sweeps += a.type == kActNorm;
+        scale_sweeps += a.type == kActScale;
+    }
+    info->launches = int64_t(p->acts.size());
+    info->passes = int64_t(passes.size()) + scale_sweeps;
+    info->alg_bytes = (double(info->passes) * 2.0 + double(norm_sweeps)) * std::ldexp(1.0, n) * amp_bytes(dtype);
     info->alg_flops = 0.0;
+    info->renorms = R;
+    // vector flops the kernels issue (a multiply counts 1, a multiply-add 2), per thread and block of E
+    // amplitudes, times the 2^n / E threads of all blocks: a dense 2x2 with a real first column 20 per
+    // pair, a general one 28 per pair it runs on, a two-qubit block 120 per group of four, a phase factor
+    // 6 per element it multiplies, a sign flip 0
+    {
+        const int E = 1 << log_e;
+        double per_thread = 0.0;
+        for (const SRound &rd : rounds) {
+            for (int j = 0; j < log_e; ++j)
+                for (int l = 0; l < kLists; ++l)
+                    for (int oi = rd.seg[kLists * j + l]; oi < rd.seg[kLists * j + l + 1]; ++oi)
+                        per_thread += l == kListCond ? 28.0 * __builtin_popcount(ops[size_t(oi)].pmask) : 20.0 * (E / 2);
+            per_thread += 120.0 * (E / 4) * (rd.pseg[npairs(log_e)] - rd.pseg[0]);
+            for (int oi = rd.seg[kLists * log_e + 1]; oi < rd.seg[kLists * log_e + 2]; ++oi)
+                per_thread += 6.0 * (__builtin_popcount(ops[size_t(oi)].m1) + __builtin_popcount(ops[size_t(oi)].m0));
+        }
+        info->issued_flops = per_thread * std::ldexp(1.0, n - log_e);
+    }
     *out = p;
     return QSIM_OK;
 }
 
 template <typename T, int LE, int LT, int MW>
-static void launch_variant(StagedPlan *p, qsim_state *s, size_t i, int init_zero)
+static void launch_variant(StagedPlan *p, qsim_state *s, size_t i, int init_zero, const double *scale, double *norm)
 {
-    hipLaunchKernelGGL((k_staged<T, LE, LT, MW>), dim3(unsigned(dim(p->n - p->m))), dim3(1 << LT), 0, s->stream,
-                       static_cast<T *>(s->data), p->d_passes + i, p->d_stages, p->d_rounds, p->d_ops, p->d_blks, init_zero);
+    if (scale || norm)
+        hipLaunchKernelGGL((k_staged<T, LE, LT, MW, true>), dim3(unsigned(dim(p->n - p->m))), dim3(1 << LT), 0, s->stream,
+                           static_cast<T *>(s->data), p->d_passes + i, p->d_stages, p->d_rounds, p->d_ops, p->d_blks, init_zero,
+                           scale, norm);
+    else
+        hipLaunchKernelGGL((k_staged<T, LE, LT, MW, false>), dim3(unsigned(dim(p->n - p->m))), dim3(1 << LT), 0, s->stream,
+                           static_cast<T *>(s->data), p->d_passes + i, p->d_stages, p->d_rounds, p->d_ops, p->d_blks, init_zero,
+                           nullptr, nullptr);
 }
 
 template <typename T, int LE, int LT, int MW>
-static void launch_half(StagedPlan *p, qsim_state *s, size_t i, int init_zero)
+static void launch_half(StagedPlan *p, qsim_state *s, size_t i, int init_zero, const double *scale, double *norm)
 {
-    hipLaunchKernelGGL((k_staged_half<T, LE, LT, MW>), dim3(unsigned(dim(p->n - p->m))), dim3(1 << LT), 0, s->stream,
-                       static_cast<T *>(s->data), p->d_passes + i, p->d_stages, p->d_rounds, p->d_ops, p->d_blks, init_zero);
+    if (scale || norm)
+        hipLaunchKernelGGL((k_staged_half<T, LE, LT, MW, true>), dim3(unsigned(dim(p->n - p->m))), dim3(1 << LT), 0, s->stream,
+                           static_cast<T *>(s->data), p->d_passes + i, p->d_stages, p->d_rounds, p->d_ops, p->d_blks, init_zero,
+                           scale, norm);
+    else
+        hipLaunchKernelGGL((k_staged_half<T, LE, LT, MW, false>), dim3(unsigned(dim(p->n - p->m))), dim3(1 << LT), 0, s->stream,
+                           static_cast<T *>(s->data), p->d_passes + i, p->d_stages, p->d_rounds, p->d_ops, p->d_blks, init_zero,
+                           nullptr, nullptr);
 }
 
 template <typename T, int LE, int LT, int MW>
-static void launch_wave(StagedPlan *p, qsim_state *s, size_t i, int init_zero)
+static void launch_wave(StagedPlan *p, qsim_state *s, size_t i, int init_zero, const double *scale, double *norm)
 {
-    hipLaunchKernelGGL((k_staged_wave<T, LE, LT, MW>), dim3(unsigned(dim(p->n - p->m))), dim3(1 << LT), 0, s->stream,
-                       static_cast<T *>(s->data), p->d_passes + i, p->d_stages, p->d_rounds, p->d_ops, p->d_blks, init_zero);
+    if (scale || norm)
+        hipLaunchKernelGGL((k_staged_wave<T, LE, LT, MW, true>), dim3(unsigned(dim(p->n - p->m))), dim3(1 << LT), 0, s->stream,
+                           static_cast<T *>(s->data), p->d_passes + i, p->d_stages, p->d_rounds, p->d_ops, p->d_blks, init_zero,
+                           scale, norm);
+    else
+        hipLaunchKernelGGL((k_staged_wave<T, LE, LT, MW, false>), dim3(unsigned(dim(p->n - p->m))), dim3(1 << LT), 0, s->stream,
+                           static_cast<T *>(s->data), p->d_passes + i, p->d_stages, p->d_rounds, p->d_ops, p->d_blks, init_zero,
+                           nullptr, nullptr);
 }
 
 // the kernel that runs pass i: the wave-split kernel where every round trip splits at a wave position
@@ -1193,30 +1300,30 @@ static int pass_variant(const StagedPlan *p, size_t i)
     return (d & 4) ? QSIM_STAGED_HALF : QSIM_STAGED_FULL;
 }
 
-static int launch_pass(StagedPlan *p, qsim_state *s, size_t i, int init_zero)
+static int launch_pass(StagedPlan *p, qsim_state *s, size_t i, int init_zero, const double *scale, double *norm)
 {
     const int v = p->log_e * 16 + p->log_t;
     const int var = pass_variant(p, i);
     if (var == QSIM_STAGED_WAVE && p->dtype == QSIM_C128) {
-        if (v == 4 * 16 + 7) launch_wave<double, 4, 7, 4>(p, s, i, init_zero);
-        else launch_wave<double, 4, 8, 4>(p, s, i, init_zero);
+        if (v == 4 * 16 + 7) launch_wave<double, 4, 7, 4>(p, s, i, init_zero, scale, norm);
+        else launch_wave<double, 4, 8, 4>(p, s, i, init_zero, scale, norm);
         QSIM_HIP(hipGetLastError());
         return QSIM_OK;
     }
     if (var == QSIM_STAGED_WAVE) {
-        if (v == 5 * 16 + 7) launch_wave<float, 5, 7, 4>(p, s, i, init_zero);
-        else launch_wave<float, 5, 8, 4>(p, s, i, init_zero);
+        if (v == 5 * 16 + 7) launch_wave<float, 5, 7, 4>(p, s, i, init_zero, scale, norm);
+        else launch_wave<float, 5, 8, 4>(p, s, i, init_zero, scale, norm);
         QSIM_HIP(hipGetLastError());
         return QSIM_OK;
     }
     if (var == QSIM_STAGED_HALF) {
         switch ((p->dtype == QSIM_C128 ? 256 : 0) + v) {
-        case 256 + 4 * 16 + 6: launch_half<double, 4, 6, 3>(p, s, i, init_zero); break;
-        case 256 + 4 * 16 + 7: launch_half<double, 4, 7, 3>(p, s, i, init_zero); break;
-        case 256 + 4 * 16 + 8: launch_half<double, 4, 8, 3>(p, s, i, init_zero); break;
-        case 5 * 16 + 6: launch_half<float, 5, 6, 3>(p, s, i, init_zero); break;
-        case 5 * 16 + 7: launch_half<float, 5, 7, 3>(p, s, i, init_zero); break;
-        case 5 * 16 + 8: launch_half<float, 5, 8, 3>(p, s, i, init_zero); break;
+        case 256 + 4 * 16 + 6: launch_half<double, 4, 6, 3>(p, s, i, init_zero, scale, norm); break;
+        case 256 + 4 * 16 + 7: launch_half<double, 4, 7, 3>(p, s, i, init_zero, scale, norm); break;
+        case 256 + 4 * 16 + 8: launch_half<double, 4, 8, 3>(p, s, i, init_zero, scale, norm); break;
+        case 5 * 16 + 6: launch_half<float, 5, 6, 3>(p, s, i, init_zero, scale, norm); break;
+        case 5 * 16 + 7: launch_half<float, 5, 7, 3>(p, s, i, init_zero, scale, norm); break;
+        case 5 * 16 + 8: launch_half<float, 5, 8, 3>(p, s, i, init_zero, scale, norm); break;
         default: return set_error(QSIM_EINVAL, "staged: no half-buffer kernel for this block shape");
         }
         QSIM_HIP(hipGetLastError());
@@ -1224,52 +1331,84 @@ static int launch_pass(StagedPlan *p, qsim_state *s, size_t i, int init_zero)
     }
     if (p->dtype == QSIM_C128) {
         switch (v) {
-        case 3 * 16 + 7: launch_variant<double, 3, 7, 4>(p, s, i, init_zero); break;
-        case 3 * 16 + 8: launch_variant<double, 3, 8, 4>(p, s, i, init_zero); break;
-        case 3 * 16 + 9: launch_variant<double, 3, 9, 3>(p, s, i, init_zero); break;
-        case 4 * 16 + 6: launch_variant<double, 4, 6, 2>(p, s, i, init_zero); break;
-        case 4 * 16 + 7: launch_variant<double, 4, 7, 2>(p, s, i, init_zero); break;
-        case 4 * 16 + 9: launch_variant<double, 4, 9, 2>(p, s, i, init_zero); break;  // 13 resident qubits, one workgroup per CU
-        default: launch_variant<double, 4, 8, 2>(p, s, i, init_zero); break;
+        case 3 * 16 + 7: launch_variant<double, 3, 7, 4>(p, s, i, init_zero, scale, norm); break;
+        case 3 * 16 + 8: launch_variant<double, 3, 8, 4>(p, s, i, init_zero, scale, norm); break;
+        case 3 * 16 + 9: launch_variant<double, 3, 9, 3>(p, s, i, init_zero, scale, norm); break;
+        case 4 * 16 + 6: launch_variant<double, 4, 6, 2>(p, s, i, init_zero, scale, norm); break;
+        case 4 * 16 + 7: launch_variant<double, 4, 7, 2>(p, s, i, init_zero, scale, norm); break;
+        case 4 * 16 + 9: launch_variant<double, 4, 9, 2>(p, s, i, init_zero, scale, norm); break;  // 13 resident qubits, one workgroup per CU
+        default: launch_variant<double, 4, 8, 2>(p, s, i, init_zero, scale, norm); break;
         }
     } else {
         switch (v) {
-        case 4 * 16 + 7: launch_variant<float, 4, 7, 3>(p, s, i, init_zero); break;
-        case 4 * 16 + 8: launch_variant<float, 4, 8, 3>(p, s, i, init_zero); break;
-        case 4 * 16 + 9: launch_variant<float, 4, 9, 2>(p, s, i, init_zero); break;
-        case 5 * 16 + 6: launch_variant<float, 5, 6, 1>(p, s, i, init_zero); break;
-        case 5 * 16 + 7: launch_variant<float, 5, 7, 1>(p, s, i, init_zero); break;
-        case 5 * 16 + 9: launch_variant<float, 5, 9, 1>(p, s, i, init_zero); break;   // 14 resident qubits, one workgroup per CU
-        case 4 * 16 + 10: launch_variant<float, 4, 10, 4>(p, s, i, init_zero); break; // 14 resident qubits, 1024 threads
-        default: launch_variant<float, 5, 8, 1>(p, s, i, init_zero); break;
+        case 4 * 16 + 7: launch_variant<float, 4, 7, 3>(p, s, i, init_zero, scale, norm); break;
+        case 4 * 16 + 8: launch_variant<float, 4, 8, 3>(p, s, i, init_zero, scale, norm); break;
+        case 4 * 16 + 9: launch_variant<float, 4, 9, 2>(p, s, i, init_zero, scale, norm); break;
+        case 5 * 16 + 6: launch_variant<float, 5, 6, 1>(p, s, i, init_zero, scale, norm); break;
+        case 5 * 16 + 7: launch_variant<float, 5, 7, 1>(p, s, i, init_zero, scale, norm); break;
+        case 5 * 16 + 9: launch_variant<float, 5, 9, 1>(p, s, i, init_zero, scale, norm); break;   // 14 resident qubits, one workgroup per CU
+        case 4 * 16 + 10: launch_variant<float, 4, 10, 4>(p, s, i, init_zero, scale, norm); break; // 14 resident qubits, 1024 threads
+        default: launch_variant<float, 5, 8, 1>(p, s, i, init_zero, scale, norm); break;
         }
     }
     QSIM_HIP(hipGetLastError());
     return QSIM_OK;
 }
 
-void staged_launch_variants(const StagedPlan *p, int32_t *variant)
+void staged_launch_list(const StagedPlan *p, int32_t *kind, int32_t *variant)
 {
-    for (size_t i = 0; i < p->passes.size(); ++i) variant[i] = pass_variant(p, i);
+    for (size_t i = 0; i < p->acts.size(); ++i) {
+        const StagedAct &a = p->acts[i];
+        if (kind) kind[i] = a.type == kActPass ? QSIM_KERNEL_STAGED : QSIM_KERNEL_RENORM;
+        if (variant) variant[i] = a.type == kActPass ? pass_variant(p, size_t(a.index)) : 0;
+    }
 }
 
-// from_zero: the first pass generates |0...0> in its loads instead of reading the state
+double *staged_norms(StagedPlan *p) { return p->d_aux; }
+
+// One launch of the plan. A pass that ends before a renormalisation point also sums its per-block
+// partials into the point's squared norm (part of the same launch step).
+static int run_act(StagedPlan *p, qsim_state *s, const StagedAct &a, bool init_zero)
+{
+    if (a.type == kActNorm) return launch_norm_into(s, p->d_aux + p->aux_l2, p->d_aux + a.index);
+    if (a.type == kActScale) return launch_renorm_scale(s, p->d_aux + a.index);
+    const size_t i = size_t(a.index);
+    const double *scale = p->scale_of[i] >= 0 ? p->d_aux + p->scale_of[i] : nullptr;
+    double *norm = p->norm_of[i] >= 0 ? p->d_aux + p->aux_part : nullptr;
+    if (int rc = launch_pass(p, s, i, init_zero, scale, norm)) return rc;
+    if (norm) return launch_sum_array(norm, dim(p->n - p->m), p->d_aux + p->aux_l2, p->d_aux + p->norm_of[i], s->stream);
+    return QSIM_OK;
+}
+
+// from_zero: the first pass generates |0...0> in its loads instead of reading the state (a plan that
+// does not start with a pass writes |0...0> first)
+static bool zero_in_first_pass(const StagedPlan *p, bool from_zero)
+{
+    return from_zero && !p->acts.empty() && p->acts[0].type == kActPass;
+}
+
 int staged_execute(StagedPlan *p, qsim_state *s, bool from_zero)
 {
-    for (size_t i = 0; i < p->passes.size(); ++i)
-        if (int rc = launch_pass(p, s, i, from_zero && i == 0)) return rc;
+    const bool zf = zero_in_first_pass(p, from_zero);
+    if (from_zero && !zf)
+        if (int rc = launch_set_basis(s, 0)) return rc;
+    for (size_t i = 0; i < p->acts.size(); ++i)
+        if (int rc = run_act(p, s, p->acts[i], zf && i == 0)) return rc;
     return QSIM_OK;
 }
 
 int staged_execute_timed(StagedPlan *p, qsim_state *s, bool from_zero, double *ms, int32_t *kind, int32_t *fk)
 {
-    const size_t L = p->passes.size();
+    const bool zf = zero_in_first_pass(p, from_zero);
+    if (from_zero && !zf)
+        if (int rc = launch_set_basis(s, 0)) return rc;
+    const size_t L = p->acts.size();
     std::vector<hipEvent_t> ev(2 * L, nullptr);
     for (auto &e : ev) QSIM_HIP(hipEventCreate(&e));
     int rc = QSIM_OK;
     for (size_t i = 0; i < L && !rc; ++i) {
         QSIM_HIP(hipEventRecord(ev[2 * i], s->stream));
-        rc = launch_pass(p, s, i, from_zero && i == 0);
+        rc = run_act(p, s, p->acts[i], zf && i == 0);
         QSIM_HIP(hipEventRecord(ev[2 * i + 1], s->stream));
     }
     if (!rc) {
@@ -1278,9 +1417,9 @@ int staged_execute_timed(StagedPlan *p, qsim_state *s, bool from_zero, double *m
             float tms = 0.f;
             QSIM_HIP(hipEventElapsedTime(&tms, ev[2 * i], ev[2 * i + 1]));
             if (ms) ms[i] = tms;
-            if (kind) kind[i] = QSIM_KERNEL_STAGED;
             if (fk) fk[i] = 0;
         }
+        staged_launch_list(p, kind, nullptr);
     }
     for (auto &e : ev) (void)hipEventDestroy(e);
     return rc;
@@ -1294,6 +1433,7 @@ void staged_free(StagedPlan *p)
     if (p->d_rounds) (void)hipFree(p->d_rounds);
     if (p->d_ops) (void)hipFree(p->d_ops);
     if (p->d_blks) (void)hipFree(p->d_blks);
+    if (p->d_aux) (void)hipFree(p->d_aux);
     delete p;
 }
 

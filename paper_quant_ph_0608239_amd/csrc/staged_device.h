@@ -547,6 +547,60 @@ __device__ __forceinline__ void run_rounds(typename Vec<T>::C *x, const SStage &
     }
 }
 
+// Renormalisation folded into a pass (Eq. STAT1). `scale` (NULL: none) points at the FP64 squared
+// norm that the previous pass left: every amplitude the pass loads is multiplied by 1/sqrt of it (by 1
+// when it is not positive), exactly as a separate rescaling sweep would. `norm` (NULL: none) receives one
+// FP64 partial sum of |a|^2 per block, over the amplitudes the pass stores; the partials are summed
+// afterwards in a fixed order.
+// The block runners take it only when instantiated with EDGE = true, so the passes that need neither
+// are compiled without it.
+struct SEdge {
+    const double *scale;
+    double *norm;
+};
+
+template <typename T, int E>
+__device__ __forceinline__ void edge_scale(typename Vec<T>::C *x, const double *scale)
+{
+    const double s = *scale;
+    const T f = static_cast<T>(s > 0.0 ? 1.0 / sqrt(s) : 1.0);
+#pragma unroll
+    for (int r = 0; r < E; ++r) {
+        x[r].x *= f;
+        x[r].y *= f;
+    }
+}
+
+template <typename T, int E>
+__device__ __forceinline__ double sq_sum(const typename Vec<T>::C *x)
+{
+    double acc = 0.0;
+#pragma unroll
+    for (int r = 0; r < E; ++r) {
+        const double re = double(x[r].x), im = double(x[r].y);
+        acc += re * re + im * im;
+    }
+    return acc;
+}
+
+// One partial sum per block: a butterfly over each wavefront, then the wavefronts' sums in order.
+// Called by every thread of the workgroup after its last LDS access of the block; leaves LDS free.
+__device__ __forceinline__ void edge_norm_out(double acc, double *norm, uint64_t blk, void *lds)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) acc += __shfl_xor(acc, o);
+    double *w = static_cast<double *>(lds);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) w[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s = 0.0;
+        for (unsigned i = 0; i < blockDim.x / 64; ++i) s += w[i];
+        norm[blk] = s;
+    }
+    __syncthreads();
+}
+
 // Addressing of a block: block `blk` of a pass holds the 2^M amplitudes whose index bits outside the
 // resident set R equal the bits of blk. In the load/store layout, thread t and element k hold local
 // index k * NT + t, so consecutive threads take consecutive local indices (contiguous runs).
@@ -600,8 +654,8 @@ __device__ __forceinline__ void regs_to_lds(const typename Vec<T>::C *v, typenam
 }
 
 template <typename T, int LOG_E, int LOG_T>
-__device__ __forceinline__ void store_block(T *__restrict__ a, const SPass &pass, uint64_t base, uint64_t dt,
-                                            const typename Vec<T>::C *lds)
+__device__ __forceinline__ double store_block(T *__restrict__ a, const SPass &pass, uint64_t base, uint64_t dt,
+                                              const typename Vec<T>::C *lds, bool want_norm)
 {
     using C = typename Vec<T>::C;
     constexpr int E = 1 << LOG_E;
@@ -612,15 +666,16 @@ __device__ __forceinline__ void store_block(T *__restrict__ a, const SPass &pass
     for (int k = 0; k < E; ++k) v[k] = lds[slot<T>(k * (1 << LOG_T) + t)];
 #pragma unroll
     for (int k = 0; k < E; ++k) st_nt(agw + elem_part<LOG_E, LOG_T>(pass, k), v[k]);
+    return want_norm ? sq_sum<T, E>(v) : 0.0;
 }
 
 // Run the stages of a pass on the block held in LDS (load/store layout in, load/store layout out).
 // Every stage reads the block into registers in its own layout, applies its rounds, and writes it
 // back (permuted by the stage-end quantum swap, if any).
-template <typename T, int LOG_E, int LOG_T>
+template <typename T, int LOG_E, int LOG_T, bool EDGE = false>
 __device__ __forceinline__ void run_stages(T *__restrict__ a, const SPass &pass, uint64_t base, cptr<SStage> stages,
                                            cptr<SRound> rounds, cptr<SOp> ops, cptr<SBlk> blks,
-                                           typename Vec<T>::C *lds, bool init_zero)
+                                           typename Vec<T>::C *lds, bool init_zero, SEdge edge, double &nacc)
 {
     using C = typename Vec<T>::C;
     constexpr int E = 1 << LOG_E;
@@ -667,6 +722,7 @@ __device__ __forceinline__ void run_stages(T *__restrict__ a, const SPass &pass,
             } else {
 #pragma unroll
                 for (int r = 0; r < E; ++r) x[r] = ld_nt(ag + gr(r));
+                if (EDGE && edge.scale) edge_scale<T, E>(x, edge.scale);
             }
         } else {
 #pragma unroll
@@ -712,16 +768,17 @@ __device__ __forceinline__ void run_stages(T *__restrict__ a, const SPass &pass,
                 if ((r >> j) & 1) v |= uint64_t(1) << st.prb[j];
             st_nt(agw + v, x[r]);
         }
+        if (EDGE && edge.norm) nacc += sq_sum<T, E>(x);
     }
 }
 
 // Process block `blk` of a pass: load it (or generate |0...0> when init_zero is set), run the
 // stages, store it. Called by every thread of a workgroup of 2^LOG_T threads; `lds` holds
 // lds_slots<T>(LOG_E + LOG_T) amplitudes.
-template <typename T, int LOG_E, int LOG_T>
+template <typename T, int LOG_E, int LOG_T, bool EDGE = false>
 __device__ __forceinline__ void run_block(T *__restrict__ a, const SPass &pass, uint64_t blk, cptr<SStage> stages,
                                           cptr<SRound> rounds, cptr<SOp> ops, cptr<SBlk> blks,
-                                          typename Vec<T>::C *lds, bool init_zero)
+                                          typename Vec<T>::C *lds, bool init_zero, SEdge edge)
 {
     using C = typename Vec<T>::C;
     constexpr int E = 1 << LOG_E;
@@ -739,12 +796,15 @@ __device__ __forceinline__ void run_block(T *__restrict__ a, const SPass &pass, 
         } else {
             C v[E];
             load_block<T, LOG_E, LOG_T>(a, pass, base, dt, v);
+            if (EDGE && edge.scale) edge_scale<T, E>(v, edge.scale);
             regs_to_lds<T, LOG_E, LOG_T>(v, lds);
         }
         __syncthreads();
     }
-    run_stages<T, LOG_E, LOG_T>(a, pass, base, stages, rounds, ops, blks, lds, init_zero);
-    if (!(pass.direct & 2)) store_block<T, LOG_E, LOG_T>(a, pass, base, dt, lds);
+    double nacc = 0.0;
+    run_stages<T, LOG_E, LOG_T, EDGE>(a, pass, base, stages, rounds, ops, blks, lds, init_zero, edge, nacc);
+    if (!(pass.direct & 2)) nacc += store_block<T, LOG_E, LOG_T>(a, pass, base, dt, lds, EDGE && edge.norm != nullptr);
+    if (EDGE && edge.norm) edge_norm_out(nacc, edge.norm, blk, lds);
     // a caller that runs the next block in this workgroup overwrites LDS: every thread must have
     // read its last values first
     __syncthreads();
@@ -804,10 +864,10 @@ __device__ __forceinline__ void exchange_half(typename Vec<T>::C *x, typename Ve
 
 // Process block `blk` of a half-buffer pass (SPass::direct bit 2): as run_block, with every LDS round
 // trip split in two by the stages' split bits. `lds` holds lds_slots<T>(LOG_E + LOG_T - 1) amplitudes.
-template <typename T, int LOG_E, int LOG_T>
+template <typename T, int LOG_E, int LOG_T, bool EDGE = false>
 __device__ __forceinline__ void run_block_half(T *__restrict__ a, const SPass &pass, uint64_t blk, cptr<SStage> stages,
                                                cptr<SRound> rounds, cptr<SOp> ops, cptr<SBlk> blks, typename Vec<T>::C *lds,
-                                               bool init_zero)
+                                               bool init_zero, SEdge edge)
 {
     using C = typename Vec<T>::C;
     constexpr int E = 1 << LOG_E;
@@ -841,6 +901,7 @@ __device__ __forceinline__ void run_block_half(T *__restrict__ a, const SPass &p
                     if ((r >> j) & 1) v |= uint64_t(1) << st.prb[j];
                 x[r] = ld_nt(ag + v);
             }
+            if (EDGE && edge.scale) edge_scale<T, E>(x, edge.scale);
         }
     } else {
         const uint64_t g0 = base | lane_part<LOG_T>(pass, t);
@@ -851,6 +912,7 @@ __device__ __forceinline__ void run_block_half(T *__restrict__ a, const SPass &p
             const C *ag = reinterpret_cast<const C *>(a) + g0;
 #pragma unroll
             for (int k = 0; k < E; ++k) x[k] = ld_nt(ag + elem_part<LOG_E, LOG_T>(pass, k));
+            if (EDGE && edge.scale) edge_scale<T, E>(x, edge.scale);
         }
         int so[E];
         half_slots<T, LOG_E>(st.rb, st.hb_in, so);
@@ -872,6 +934,7 @@ __device__ __forceinline__ void run_block_half(T *__restrict__ a, const SPass &p
         st = nx;
         et = nt;
     }
+    double nacc = 0.0;
     if (pass.direct & 2) {
         uint64_t gt = base;
 #pragma unroll
@@ -886,6 +949,7 @@ __device__ __forceinline__ void run_block_half(T *__restrict__ a, const SPass &p
                 if ((r >> j) & 1) v |= uint64_t(1) << st.prb[j];
             st_nt(agw + v, x[r]);
         }
+        if (EDGE && edge.norm) nacc = sq_sum<T, E>(x);
     } else {
         int so[E];
         half_slots<T, LOG_E>(st.rb, st.hb_out, so);
@@ -894,7 +958,9 @@ __device__ __forceinline__ void run_block_half(T *__restrict__ a, const SPass &p
         C *agw = reinterpret_cast<C *>(a) + (base | lane_part<LOG_T>(pass, t));
 #pragma unroll
         for (int k = 0; k < E; ++k) st_nt(agw + elem_part<LOG_E, LOG_T>(pass, k), x[k]);
+        if (EDGE && edge.norm) nacc = sq_sum<T, E>(x);
     }
+    if (EDGE && edge.norm) edge_norm_out(nacc, edge.norm, blk, lds);
 }
 
 // ---- wave-split half-buffer passes ----------------------------------------------------------------
@@ -945,10 +1011,10 @@ __device__ __forceinline__ void wave_in(typename Vec<T>::C *x, const typename Ve
 
 // Process block `blk` of a wave-split pass (SPass::direct bits 2 and 3). `lds` holds
 // lds_slots<T>(LOG_E + LOG_T - 1) amplitudes.
-template <typename T, int LOG_E, int LOG_T>
+template <typename T, int LOG_E, int LOG_T, bool EDGE = false>
 __device__ __forceinline__ void run_block_wave(T *__restrict__ a, const SPass &pass, uint64_t blk, cptr<SStage> stages,
                                                cptr<SRound> rounds, cptr<SOp> ops, cptr<SBlk> blks, typename Vec<T>::C *lds,
-                                               bool init_zero)
+                                               bool init_zero, SEdge edge)
 {
     using C = typename Vec<T>::C;
     constexpr int E = 1 << LOG_E;
@@ -984,6 +1050,7 @@ __device__ __forceinline__ void run_block_wave(T *__restrict__ a, const SPass &p
                         if ((r >> j) & 1) v |= uint64_t(1) << st.prb[j];
                     x[r] = ld_nt(ag + v);
                 }
+                if (EDGE && edge.scale) edge_scale<T, E>(x, edge.scale);
             }
         } else {
             if (first) {
@@ -996,6 +1063,7 @@ __device__ __forceinline__ void run_block_wave(T *__restrict__ a, const SPass &p
                     const C *ag = reinterpret_cast<const C *>(a) + g0;
 #pragma unroll
                     for (int k = 0; k < E; ++k) x[k] = ld_nt(ag + elem_part<LOG_E, LOG_T>(pass, k));
+                    if (EDGE && edge.scale) edge_scale<T, E>(x, edge.scale);
                 }
                 wave_out<T, E>(x, lds, slot<T>(int(squeeze(uint32_t(t), st.hb_in))), lso, st.hj_in, false);
             }
@@ -1012,6 +1080,7 @@ __device__ __forceinline__ void run_block_wave(T *__restrict__ a, const SPass &p
     // storing after the stage loop keeps every load of the op tables ahead of the first store to the
     // state (scalar loads stay legal)
     const SStage st = ldc<SStage>(stages + (pass.stage_end - 1));
+    double nacc = 0.0;
     if (pass.direct & 2) {
         uint64_t gt = base;
 #pragma unroll
@@ -1026,6 +1095,7 @@ __device__ __forceinline__ void run_block_wave(T *__restrict__ a, const SPass &p
                 if ((r >> j) & 1) v |= uint64_t(1) << st.prb[j];
             st_nt(agw + v, x[r]);
         }
+        if (EDGE && edge.norm) nacc = sq_sum<T, E>(x);
     } else {
         uint32_t et = 0;
 #pragma unroll
@@ -1039,7 +1109,10 @@ __device__ __forceinline__ void run_block_wave(T *__restrict__ a, const SPass &p
         C *agw = reinterpret_cast<C *>(a) + g0;
 #pragma unroll
         for (int k = 0; k < E; ++k) st_nt(agw + elem_part<LOG_E, LOG_T>(pass, k), x[k]);
+        if (EDGE && edge.norm) nacc = sq_sum<T, E>(x);
     }
+    // every wavefront reaches this point after the same number of barriers, so the ones below pair up
+    if (EDGE && edge.norm) edge_norm_out(nacc, edge.norm, blk, lds);
 }
 
 // host: append the schedule of one circuit (see staged.hip)

@@ -49,7 +49,7 @@ def test_binding_covers_header():
 def test_gate_struct_layout():
     from paper_quant_ph_0608239_amd import _lib
     assert ctypes.sizeof(_lib.Gate) == 96
-    assert ctypes.sizeof(_lib.PlanInfo) == 56
+    assert ctypes.sizeof(_lib.PlanInfo) == 72
 
 
 def _plan(L, n, gates, method=0, dtype=1):
@@ -80,7 +80,7 @@ def test_validation_rejects_before_device(L):
     assert b"null" in L.qsim_last_error()
     for bad in [_g("H", 4), _g("X", 1, controls=0b10), _g("X", 0, controls=1 << 4),
                 _g("SWAP", 1, t2=1), _g("SWAP", 1, t2=9), _g("PHASE", 0, theta=float("nan")), _g("RK", 0, t2=64),
-                _g("RKDG", 1, t2=-1)]:
+                _g("RKDG", 1, t2=-1), _g("RENORM", 2), _g("RENORM", 0, controls=0b10)]:
         rc, _ = _plan(L, 4, [bad])
         assert rc == _lib.EINVAL, (bad.op, bad.target)
     g = _g("H", 0)
@@ -106,13 +106,26 @@ def test_plain_plan_bookkeeping(L):
     L.qsim_plan_free(h)
 
 
+def test_plan_norms_validation(L):
+    from paper_quant_ph_0608239_amd import _lib
+    assert L.qsim_plan_get_norms(None, None, 0) == _lib.EINVAL
+    rc, h = _plan(L, 6, [_g("H", 1)])
+    assert rc == 0
+    out = (ctypes.c_double * 2)()
+    assert L.qsim_plan_get_norms(h, out, 1) == _lib.EINVAL  # the plan has no renormalisation point
+    assert L.qsim_plan_get_norms(h, out, -1) == _lib.EINVAL
+    assert L.qsim_plan_get_norms(h, None, 0) == 0
+    L.qsim_plan_free(h)
+
+
 def test_circuit_parser_maps_keywords():
     import qsim_workloads as wl
     from paper_quant_ph_0608239_amd import parse_circuit, _lib
     text = wl.circuit_text(5, ["H 0", "CNOT 0 1", "TOFFOLI 0 1 2", "CRK 1 3 4", "CRKDG 1 3 4", "QSWAP 0 4",
-                               "CV 2 3 0x1.8p+0", "RZ 4 0.5", "U 2 1 0 0 0 0 0 1 0"], initial_state=3)
+                               "CV 2 3 0x1.8p+0", "RZ 4 0.5", "U 2 1 0 0 0 0 0 1 0", "RENORM"],
+                           initial_state=3)
     c = parse_circuit(text)
-    assert c.n == 5 and c.init == 3 and len(c.gates) == 9
+    assert c.n == 5 and c.init == 3 and len(c.gates) == 10
     g = c.gates
     assert (g[1].op, g[1].target, g[1].controls) == (_lib.OPS["X"], 1, 1)
     assert (g[2].op, g[2].target, g[2].controls) == (_lib.OPS["X"], 2, 3)
@@ -121,3 +134,4 @@ def test_circuit_parser_maps_keywords():
     assert (g[4].op, g[4].target, g[4].target2, g[4].controls) == (_lib.OPS["RKDG"], 3, 4, 2)
     assert (g[5].op, g[5].target, g[5].target2) == (_lib.OPS["SWAP"], 0, 4)
     assert g[6].theta == 1.5 and g[7].theta == 0.5 and list(g[8].u) == [1, 0, 0, 0, 0, 0, 1, 0]
+    assert (g[9].op, g[9].target, g[9].controls) == (_lib.OPS["RENORM"], 0, 0)

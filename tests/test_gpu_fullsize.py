@@ -277,25 +277,25 @@ C64_SEED = 31  # the complex64 brickwork uses its own seed
 
 
 def run_renormalised(q, s, n, layers, method, every=10, lds=0, regs=0):
-    """Layers in groups of `every`, each group one plan, FP64 renormalisation after each group.
-    Returns the norms measured before each renormalisation."""
-    norms = []
-    s.set_basis(0)
-    for a in range(0, layers, every):
-        b = min(layers, a + every)
-        c = q.parse_circuit(wl.brickwork_circuit(n, layers, seed=C64_SEED, layer_range=(a, b)))
-        p = plan_for(q, c, "c64", method, lds, regs)
-        p.execute(s)
-        p.close()
-        norms.append(s.renormalize())
-        say(f"  layers {a}..{b - 1}: norm before renormalisation = {norms[-1]!r}")
+    """The brickwork as one plan with a RENORM point after every `every` layers (a staged plan folds
+    each point into the passes around it), run from |0...0>. Returns the squared norms found at the
+    points, each just before its rescaling."""
+    points = tuple(range(every, layers + 1, every))
+    c = q.parse_circuit(wl.brickwork_circuit(n, layers, seed=C64_SEED, renorm_after=points))
+    p = plan_for(q, c, "c64", method, lds, regs)
+    p.execute_from_zero(s)
+    norms = [float(x) for x in p.norms()]
+    kind, _ = p.launches()
+    p.close()
+    say(f"  {method}: {len(kind)} launches, {int(np.sum(kind == q.KERNEL_RENORM))} renormalisation sweeps; "
+        f"squared norms at the points = {norms}")
     return norms
 
 
 @pytest.fixture(scope="module")
 def brick28_ref(oracle_mod):
-    say("brick28: FP64 oracle on the 28-qubit brickwork (20 layers)")
-    return oracle_mod.run_circuit(wl.brickwork_circuit(28, 20, seed=C64_SEED))
+    say("brick28: FP64 oracle on the 28-qubit brickwork (20 layers, renormalised after layers 10 and 20)")
+    return oracle_mod.run_circuit(wl.brickwork_circuit(28, 20, seed=C64_SEED, renorm_after=(10, 20)))
 
 
 @pytest.mark.parametrize("method", ["fused", "staged"])

@@ -376,6 +376,74 @@ def test_staged_every_variant(q, oracle_mod, dtype, m, le):
         s.close()
 
 
+# renormalisation points: before the first layer (no pass before it), in the middle, twice in a row,
+# and at the end (no pass after it)
+RENORM_AFTER = (0, 2, 4, 4, 6)
+RENORM_PLANS = [("c128", "plain", 0, 0), ("c128", "fused", 0, 0), ("c128", "staged", 12, 4), ("c128", "staged", 11, 3),
+                ("c64", "plain", 0, 0), ("c64", "staged", 13, 5), ("c64", "staged", 12, 4)]
+
+
+@pytest.mark.parametrize("dtype,method,m,le", RENORM_PLANS)
+def test_plan_renormalisation_points(q, oracle_mod, dtype, method, m, le):
+    """RENORM inside plans (Eq. STAT1) against the oracle, which renormalises at the same points: the
+    final state, and the squared norm found at every point, from an unnormalised start state; again
+    from |0...0>, and (staged) timed and through a replayed graph. A staged plan folds the norm into
+    the pass before a point and the factor into the pass after it, so only the points with no pass on
+    one side run sweeps: the norm of the first point, a factor and a norm around the repeated point,
+    and the factor of the last."""
+    n, layers, seed = 16, 6, 31
+    text = wl.brickwork_circuit(n, layers, seed, renorm_after=RENORM_AFTER)
+    c = q.parse_circuit(text)
+    psi0 = 2.5 * wl.gaussian_state(n, 8)
+    ref = oracle_mod.run_circuit(text, psi0=psi0)
+    ops = [ln.split()[0] for ln in text.splitlines() if ln.strip() and not ln.startswith(("!", "#", "QUBITS"))]
+    at = [i for i, kw in enumerate(ops) if kw == "RENORM"]
+    want_norms = np.array([oracle_mod.norm(oracle_mod.run_circuit(text, psi0=psi0, ops_limit=k)) for k in at])
+    rtol = 1e-12 if dtype == "c128" else 1e-5
+    opts = dict(method=method, lds_qubits=m, lds_regs=le)
+    p = q.Plan(c, dtype, **opts)
+    assert p.info["renorms"] == len(RENORM_AFTER)
+    kind, var = p.launches()
+    sweeps = int(np.sum(kind == q.KERNEL_RENORM))
+    assert sweeps == (4 if method == "staged" else len(RENORM_AFTER)), (method, list(kind))
+    print(f"renorm {dtype} {method} m={m} le={le}: {len(kind)} launches, {sweeps} sweeps", flush=True)
+    s = gpu_state(q, psi0, dtype)
+    p.execute(s)
+    compare_circuit(s.download().astype(np.complex128), ref, dtype, f"{method} renorm")
+    np.testing.assert_allclose(p.norms(), want_norms, rtol=rtol)
+    # from |0...0>: the first point's norm is 1
+    ref0 = oracle_mod.run_circuit(text)
+    want0 = np.array([oracle_mod.norm(oracle_mod.run_circuit(text, ops_limit=k)) for k in at])
+    s.upload(psi0)
+    p.execute_from_zero(s)
+    compare_circuit(s.download().astype(np.complex128), ref0, dtype, f"{method} renorm from zero")
+    np.testing.assert_allclose(p.norms(), want0, rtol=rtol)
+    s.upload(psi0)
+    ms, kd, fk = p.execute_timed(s)
+    assert len(ms) == p.info["launches"] and np.array_equal(kd, kind)
+    compare_circuit(s.download().astype(np.complex128), ref, dtype, f"{method} renorm timed")
+    p.close()
+    s.close()
+    if method == "staged":
+        import torch
+        with torch.cuda.stream(torch.cuda.Stream()):
+            g = q.Plan(c, dtype, use_graph=True, **opts)
+            s2 = q.State(n, dtype)
+            for rep in range(3):  # capture, then replays, with eager work and synchronisation between
+                s2.upload(psi0)
+                g.execute(s2)
+                compare_circuit(s2.download().astype(np.complex128), ref, dtype, f"staged renorm graph run {rep}")
+                np.testing.assert_allclose(g.norms(), want_norms, rtol=rtol)
+            g.close()
+            s2.close()
+
+
+def test_renorm_point_rejected_outside_plans(q):
+    c = q.parse_circuit(wl.circuit_text(4, ["H 0", "RENORM"]))
+    with pytest.raises(q.QsimError):
+        q.Batch([c], "c128")
+
+
 @pytest.mark.parametrize("method", ["plain", "fused"])
 def test_execute_from_zero_unstaged(q, oracle_mod, method):
     n = 12
