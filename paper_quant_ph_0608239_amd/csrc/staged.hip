@@ -33,53 +33,58 @@ using namespace staged;
 
 namespace {
 
+// Kernel instantiations per pass (MODE): 0 reads the state and folds no renormalisation; 1 folds a
+// renormalisation point (scales its loads and/or sums the norm of its stores); 2 is the first pass of a
+// run from |0...0>, which generates the initial state instead of loading it (and may sum the norm).
+// Passes of mode 0 thus compile without the code of the other two, which would cost registers.
+//
 // One pass over the whole state: one workgroup per block of 2^(LOG_E + LOG_T) amplitudes. (A
 // persistent grid that prefetches each workgroup's next block into registers while the current one
 // is processed measured slower on gfx950: the extra registers and the wait for the previous block's
 // stores cost more than the overlap gained.)
-template <typename T, int LOG_E, int LOG_T, int MINW, bool EDGE>
+template <typename T, int LOG_E, int LOG_T, int MINW, int MODE>
 __global__ __launch_bounds__(1 << LOG_T, MINW) void k_staged(T *__restrict__ a, const SPass *__restrict__ passp,
                                                              const SStage *__restrict__ stages, const SRound *__restrict__ rounds,
                                                              const SOp *__restrict__ ops, const SBlk *__restrict__ blks,
-                                                             int init_zero, const double *scale, double *norm)
+                                                             const double *scale, double *norm)
 {
     using C = typename Vec<T>::C;
     __shared__ C lds[lds_slots<T>(LOG_E + LOG_T)];
     const SPass pass = ldc<SPass>(as_const(passp));
-    run_block<T, LOG_E, LOG_T, EDGE>(a, pass, blockIdx.x, as_const(stages), as_const(rounds), as_const(ops), as_const(blks), lds,
-                               init_zero != 0, SEdge{scale, norm});
+    run_block<T, LOG_E, LOG_T, MODE != 0>(a, pass, blockIdx.x, as_const(stages), as_const(rounds), as_const(ops), as_const(blks), lds,
+                               MODE == 2, SEdge{scale, norm});
 }
 
 // The same pass with a buffer of half the block (every LDS round trip in two halves): twice the
 // workgroups per CU where LDS, not registers, bounds the occupancy.
-template <typename T, int LOG_E, int LOG_T, int MINW, bool EDGE>
+template <typename T, int LOG_E, int LOG_T, int MINW, int MODE>
 __global__ __launch_bounds__(1 << LOG_T, MINW) void k_staged_half(T *__restrict__ a, const SPass *__restrict__ passp,
                                                                   const SStage *__restrict__ stages,
                                                                   const SRound *__restrict__ rounds,
                                                                   const SOp *__restrict__ ops, const SBlk *__restrict__ blks,
-                                                                  int init_zero, const double *scale, double *norm)
+                                                                  const double *scale, double *norm)
 {
     using C = typename Vec<T>::C;
     __shared__ C lds[lds_slots<T>(LOG_E + LOG_T - 1)];
     const SPass pass = ldc<SPass>(as_const(passp));
-    run_block_half<T, LOG_E, LOG_T, EDGE>(a, pass, blockIdx.x, as_const(stages), as_const(rounds), as_const(ops), as_const(blks), lds,
-                                    init_zero != 0, SEdge{scale, norm});
+    run_block_half<T, LOG_E, LOG_T, MODE != 0>(a, pass, blockIdx.x, as_const(stages), as_const(rounds), as_const(ops), as_const(blks), lds,
+                                    MODE == 2, SEdge{scale, norm});
 }
 
 // The half-buffer pass when every split is at a wave position: uniform split branches, and the block
 // fits in 128 VGPRs, so four 256-thread workgroups share a CU.
-template <typename T, int LOG_E, int LOG_T, int MINW, bool EDGE>
+template <typename T, int LOG_E, int LOG_T, int MINW, int MODE>
 __global__ __launch_bounds__(1 << LOG_T, MINW) void k_staged_wave(T *__restrict__ a, const SPass *__restrict__ passp,
                                                                   const SStage *__restrict__ stages,
                                                                   const SRound *__restrict__ rounds,
                                                                   const SOp *__restrict__ ops, const SBlk *__restrict__ blks,
-                                                                  int init_zero, const double *scale, double *norm)
+                                                                  const double *scale, double *norm)
 {
     using C = typename Vec<T>::C;
     __shared__ C lds[lds_slots<T>(LOG_E + LOG_T - 1)];
     const SPass pass = ldc<SPass>(as_const(passp));
-    run_block_wave<T, LOG_E, LOG_T, EDGE>(a, pass, blockIdx.x, as_const(stages), as_const(rounds), as_const(ops), as_const(blks), lds,
-                                    init_zero != 0, SEdge{scale, norm});
+    run_block_wave<T, LOG_E, LOG_T, MODE != 0>(a, pass, blockIdx.x, as_const(stages), as_const(rounds), as_const(ops), as_const(blks), lds,
+                                    MODE == 2, SEdge{scale, norm});
 }
 
 }  // namespace
@@ -1250,43 +1255,70 @@ int staged_build(int n, int dtype, const std::vector<qsim_gate> &gates, int lds_
     return QSIM_OK;
 }
 
+// the instantiation a pass launch needs (see the kernels)
+static int pass_mode(int init_zero, const double *scale, double *norm) { return init_zero ? 2 : (scale || norm) ? 1 : 0; }
+
 template <typename T, int LE, int LT, int MW>
 static void launch_variant(StagedPlan *p, qsim_state *s, size_t i, int init_zero, const double *scale, double *norm)
 {
-    if (scale || norm)
-        hipLaunchKernelGGL((k_staged<T, LE, LT, MW, true>), dim3(unsigned(dim(p->n - p->m))), dim3(1 << LT), 0, s->stream,
-                           static_cast<T *>(s->data), p->d_passes + i, p->d_stages, p->d_rounds, p->d_ops, p->d_blks, init_zero,
-                           scale, norm);
-    else
-        hipLaunchKernelGGL((k_staged<T, LE, LT, MW, false>), dim3(unsigned(dim(p->n - p->m))), dim3(1 << LT), 0, s->stream,
-                           static_cast<T *>(s->data), p->d_passes + i, p->d_stages, p->d_rounds, p->d_ops, p->d_blks, init_zero,
-                           nullptr, nullptr);
+    const dim3 grid(unsigned(dim(p->n - p->m))), block(1 << LT);
+    T *a = static_cast<T *>(s->data);
+    switch (pass_mode(init_zero, scale, norm)) {
+    case 0:
+        hipLaunchKernelGGL((k_staged<T, LE, LT, MW, 0>), grid, block, 0, s->stream, a, p->d_passes + i, p->d_stages, p->d_rounds,
+                           p->d_ops, p->d_blks, nullptr, nullptr);
+        break;
+    case 1:
+        hipLaunchKernelGGL((k_staged<T, LE, LT, MW, 1>), grid, block, 0, s->stream, a, p->d_passes + i, p->d_stages, p->d_rounds,
+                           p->d_ops, p->d_blks, scale, norm);
+        break;
+    default:
+        hipLaunchKernelGGL((k_staged<T, LE, LT, MW, 2>), grid, block, 0, s->stream, a, p->d_passes + i, p->d_stages, p->d_rounds,
+                           p->d_ops, p->d_blks, scale, norm);
+        break;
+    }
 }
 
 template <typename T, int LE, int LT, int MW>
 static void launch_half(StagedPlan *p, qsim_state *s, size_t i, int init_zero, const double *scale, double *norm)
 {
-    if (scale || norm)
-        hipLaunchKernelGGL((k_staged_half<T, LE, LT, MW, true>), dim3(unsigned(dim(p->n - p->m))), dim3(1 << LT), 0, s->stream,
-                           static_cast<T *>(s->data), p->d_passes + i, p->d_stages, p->d_rounds, p->d_ops, p->d_blks, init_zero,
-                           scale, norm);
-    else
-        hipLaunchKernelGGL((k_staged_half<T, LE, LT, MW, false>), dim3(unsigned(dim(p->n - p->m))), dim3(1 << LT), 0, s->stream,
-                           static_cast<T *>(s->data), p->d_passes + i, p->d_stages, p->d_rounds, p->d_ops, p->d_blks, init_zero,
-                           nullptr, nullptr);
+    const dim3 grid(unsigned(dim(p->n - p->m))), block(1 << LT);
+    T *a = static_cast<T *>(s->data);
+    switch (pass_mode(init_zero, scale, norm)) {
+    case 0:
+        hipLaunchKernelGGL((k_staged_half<T, LE, LT, MW, 0>), grid, block, 0, s->stream, a, p->d_passes + i, p->d_stages, p->d_rounds,
+                           p->d_ops, p->d_blks, nullptr, nullptr);
+        break;
+    case 1:
+        hipLaunchKernelGGL((k_staged_half<T, LE, LT, MW, 1>), grid, block, 0, s->stream, a, p->d_passes + i, p->d_stages, p->d_rounds,
+                           p->d_ops, p->d_blks, scale, norm);
+        break;
+    default:
+        hipLaunchKernelGGL((k_staged_half<T, LE, LT, MW, 2>), grid, block, 0, s->stream, a, p->d_passes + i, p->d_stages, p->d_rounds,
+                           p->d_ops, p->d_blks, scale, norm);
+        break;
+    }
 }
 
 template <typename T, int LE, int LT, int MW>
 static void launch_wave(StagedPlan *p, qsim_state *s, size_t i, int init_zero, const double *scale, double *norm)
 {
-    if (scale || norm)
-        hipLaunchKernelGGL((k_staged_wave<T, LE, LT, MW, true>), dim3(unsigned(dim(p->n - p->m))), dim3(1 << LT), 0, s->stream,
-                           static_cast<T *>(s->data), p->d_passes + i, p->d_stages, p->d_rounds, p->d_ops, p->d_blks, init_zero,
-                           scale, norm);
-    else
-        hipLaunchKernelGGL((k_staged_wave<T, LE, LT, MW, false>), dim3(unsigned(dim(p->n - p->m))), dim3(1 << LT), 0, s->stream,
-                           static_cast<T *>(s->data), p->d_passes + i, p->d_stages, p->d_rounds, p->d_ops, p->d_blks, init_zero,
-                           nullptr, nullptr);
+    const dim3 grid(unsigned(dim(p->n - p->m))), block(1 << LT);
+    T *a = static_cast<T *>(s->data);
+    switch (pass_mode(init_zero, scale, norm)) {
+    case 0:
+        hipLaunchKernelGGL((k_staged_wave<T, LE, LT, MW, 0>), grid, block, 0, s->stream, a, p->d_passes + i, p->d_stages, p->d_rounds,
+                           p->d_ops, p->d_blks, nullptr, nullptr);
+        break;
+    case 1:
+        hipLaunchKernelGGL((k_staged_wave<T, LE, LT, MW, 1>), grid, block, 0, s->stream, a, p->d_passes + i, p->d_stages, p->d_rounds,
+                           p->d_ops, p->d_blks, scale, norm);
+        break;
+    default:
+        hipLaunchKernelGGL((k_staged_wave<T, LE, LT, MW, 2>), grid, block, 0, s->stream, a, p->d_passes + i, p->d_stages, p->d_rounds,
+                           p->d_ops, p->d_blks, scale, norm);
+        break;
+    }
 }
 
 // the kernel that runs pass i: the wave-split kernel where every round trip splits at a wave position
