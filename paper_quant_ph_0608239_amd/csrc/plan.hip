@@ -402,6 +402,7 @@ int qsim_plan_create(int n, int dtype, const qsim_gate *gates, int64_t ngates, c
         const size_t words = aux_l2_offset(p) + kAuxLevel2;
         hipError_t e = hipMalloc(&p->d_aux, sizeof(double) * words);
         if (e == hipSuccess) e = hipMemset(p->d_aux, 0, sizeof(double) * words);
+        if (e == hipSuccess) e = hipDeviceSynchronize();  // zeroed before any stream can use the plan
         if (e != hipSuccess) rc = hip_error(e, "plan renormalisation buffer");
     }
     if (rc) {

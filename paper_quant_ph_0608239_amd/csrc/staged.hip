@@ -1197,6 +1197,7 @@ int staged_build(int n, int dtype, const std::vector<qsim_gate> &gates, int lds_
         const size_t words = p->aux_part + (norm_in_pass ? size_t(dim(n - m)) : 0);
         e = hipMalloc(&p->d_aux, sizeof(double) * words);
         if (e == hipSuccess) e = hipMemset(p->d_aux, 0, sizeof(double) * words);
+        if (e == hipSuccess) e = hipDeviceSynchronize();  // zeroed before any stream can use the plan
     }
     if (e == hipSuccess) e = hipMalloc(&p->d_stages, sizeof(SStage) * std::max<size_t>(1, stages.size()));
     if (e == hipSuccess) e = hipMalloc(&p->d_rounds, sizeof(SRound) * std::max<size_t>(1, rounds.size()));
