@@ -41,7 +41,8 @@ def log(msg: str) -> None:
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-KERNEL_SOURCES = {"staged": ("staged.hip", "staged_device.h", "qsim_internal.h"),
+KERNEL_SOURCES = {"staged": ("staged.hip", "staged_device.h", "staged_kernels.h", "staged_k128.hip", "staged_k128w.hip",
+                             "staged_k64.hip", "staged_k64w.hip", "qsim_internal.h"),
                   "fused": ("fused.hip", "qsim_internal.h"),
                   "sweep": ("sweep.hip", "qsim_internal.h")}
 

@@ -31,64 +31,6 @@ namespace qsim {
 
 using namespace staged;
 
-namespace {
-
-// Kernel instantiations per pass (MODE): 0 reads the state and folds no renormalisation; 1 folds a
-// renormalisation point (scales its loads and/or sums the norm of its stores); 2 is the first pass of a
-// run from |0...0>, which generates the initial state instead of loading it (and may sum the norm).
-// Passes of mode 0 thus compile without the code of the other two, which would cost registers.
-//
-// One pass over the whole state: one workgroup per block of 2^(LOG_E + LOG_T) amplitudes. (A
-// persistent grid that prefetches each workgroup's next block into registers while the current one
-// is processed measured slower on gfx950: the extra registers and the wait for the previous block's
-// stores cost more than the overlap gained.)
-template <typename T, int LOG_E, int LOG_T, int MINW, int MODE>
-__global__ __launch_bounds__(1 << LOG_T, MINW) void k_staged(T *__restrict__ a, const SPass *__restrict__ passp,
-                                                             const SStage *__restrict__ stages, const SRound *__restrict__ rounds,
-                                                             const SOp *__restrict__ ops, const SBlk *__restrict__ blks,
-                                                             const double *scale, double *norm)
-{
-    using C = typename Vec<T>::C;
-    __shared__ C lds[lds_slots<T>(LOG_E + LOG_T)];
-    const SPass pass = ldc<SPass>(as_const(passp));
-    run_block<T, LOG_E, LOG_T, MODE != 0>(a, pass, blockIdx.x, as_const(stages), as_const(rounds), as_const(ops), as_const(blks), lds,
-                               MODE == 2, SEdge{scale, norm});
-}
-
-// The same pass with a buffer of half the block (every LDS round trip in two halves): twice the
-// workgroups per CU where LDS, not registers, bounds the occupancy.
-template <typename T, int LOG_E, int LOG_T, int MINW, int MODE>
-__global__ __launch_bounds__(1 << LOG_T, MINW) void k_staged_half(T *__restrict__ a, const SPass *__restrict__ passp,
-                                                                  const SStage *__restrict__ stages,
-                                                                  const SRound *__restrict__ rounds,
-                                                                  const SOp *__restrict__ ops, const SBlk *__restrict__ blks,
-                                                                  const double *scale, double *norm)
-{
-    using C = typename Vec<T>::C;
-    __shared__ C lds[lds_slots<T>(LOG_E + LOG_T - 1)];
-    const SPass pass = ldc<SPass>(as_const(passp));
-    run_block_half<T, LOG_E, LOG_T, MODE != 0>(a, pass, blockIdx.x, as_const(stages), as_const(rounds), as_const(ops), as_const(blks), lds,
-                                    MODE == 2, SEdge{scale, norm});
-}
-
-// The half-buffer pass when every split is at a wave position: uniform split branches, and the block
-// fits in 128 VGPRs, so four 256-thread workgroups share a CU.
-template <typename T, int LOG_E, int LOG_T, int MINW, int MODE>
-__global__ __launch_bounds__(1 << LOG_T, MINW) void k_staged_wave(T *__restrict__ a, const SPass *__restrict__ passp,
-                                                                  const SStage *__restrict__ stages,
-                                                                  const SRound *__restrict__ rounds,
-                                                                  const SOp *__restrict__ ops, const SBlk *__restrict__ blks,
-                                                                  const double *scale, double *norm)
-{
-    using C = typename Vec<T>::C;
-    __shared__ C lds[lds_slots<T>(LOG_E + LOG_T - 1)];
-    const SPass pass = ldc<SPass>(as_const(passp));
-    run_block_wave<T, LOG_E, LOG_T, MODE != 0>(a, pass, blockIdx.x, as_const(stages), as_const(rounds), as_const(ops), as_const(blks), lds,
-                                    MODE == 2, SEdge{scale, norm});
-}
-
-}  // namespace
-
 namespace staged {
 // factors of angle-defined diagonal operations, evaluated once per plan in FP64 on the device, and
 // the FP32 copy of every op's coefficients
@@ -1256,72 +1198,6 @@ int staged_build(int n, int dtype, const std::vector<qsim_gate> &gates, int lds_
     return QSIM_OK;
 }
 
-// the instantiation a pass launch needs (see the kernels)
-static int pass_mode(int init_zero, const double *scale, double *norm) { return init_zero ? 2 : (scale || norm) ? 1 : 0; }
-
-template <typename T, int LE, int LT, int MW>
-static void launch_variant(StagedPlan *p, qsim_state *s, size_t i, int init_zero, const double *scale, double *norm)
-{
-    const dim3 grid(unsigned(dim(p->n - p->m))), block(1 << LT);
-    T *a = static_cast<T *>(s->data);
-    switch (pass_mode(init_zero, scale, norm)) {
-    case 0:
-        hipLaunchKernelGGL((k_staged<T, LE, LT, MW, 0>), grid, block, 0, s->stream, a, p->d_passes + i, p->d_stages, p->d_rounds,
-                           p->d_ops, p->d_blks, nullptr, nullptr);
-        break;
-    case 1:
-        hipLaunchKernelGGL((k_staged<T, LE, LT, MW, 1>), grid, block, 0, s->stream, a, p->d_passes + i, p->d_stages, p->d_rounds,
-                           p->d_ops, p->d_blks, scale, norm);
-        break;
-    default:
-        hipLaunchKernelGGL((k_staged<T, LE, LT, MW, 2>), grid, block, 0, s->stream, a, p->d_passes + i, p->d_stages, p->d_rounds,
-                           p->d_ops, p->d_blks, scale, norm);
-        break;
-    }
-}
-
-template <typename T, int LE, int LT, int MW>
-static void launch_half(StagedPlan *p, qsim_state *s, size_t i, int init_zero, const double *scale, double *norm)
-{
-    const dim3 grid(unsigned(dim(p->n - p->m))), block(1 << LT);
-    T *a = static_cast<T *>(s->data);
-    switch (pass_mode(init_zero, scale, norm)) {
-    case 0:
-        hipLaunchKernelGGL((k_staged_half<T, LE, LT, MW, 0>), grid, block, 0, s->stream, a, p->d_passes + i, p->d_stages, p->d_rounds,
-                           p->d_ops, p->d_blks, nullptr, nullptr);
-        break;
-    case 1:
-        hipLaunchKernelGGL((k_staged_half<T, LE, LT, MW, 1>), grid, block, 0, s->stream, a, p->d_passes + i, p->d_stages, p->d_rounds,
-                           p->d_ops, p->d_blks, scale, norm);
-        break;
-    default:
-        hipLaunchKernelGGL((k_staged_half<T, LE, LT, MW, 2>), grid, block, 0, s->stream, a, p->d_passes + i, p->d_stages, p->d_rounds,
-                           p->d_ops, p->d_blks, scale, norm);
-        break;
-    }
-}
-
-template <typename T, int LE, int LT, int MW>
-static void launch_wave(StagedPlan *p, qsim_state *s, size_t i, int init_zero, const double *scale, double *norm)
-{
-    const dim3 grid(unsigned(dim(p->n - p->m))), block(1 << LT);
-    T *a = static_cast<T *>(s->data);
-    switch (pass_mode(init_zero, scale, norm)) {
-    case 0:
-        hipLaunchKernelGGL((k_staged_wave<T, LE, LT, MW, 0>), grid, block, 0, s->stream, a, p->d_passes + i, p->d_stages, p->d_rounds,
-                           p->d_ops, p->d_blks, nullptr, nullptr);
-        break;
-    case 1:
-        hipLaunchKernelGGL((k_staged_wave<T, LE, LT, MW, 1>), grid, block, 0, s->stream, a, p->d_passes + i, p->d_stages, p->d_rounds,
-                           p->d_ops, p->d_blks, scale, norm);
-        break;
-    default:
-        hipLaunchKernelGGL((k_staged_wave<T, LE, LT, MW, 2>), grid, block, 0, s->stream, a, p->d_passes + i, p->d_stages, p->d_rounds,
-                           p->d_ops, p->d_blks, scale, norm);
-        break;
-    }
-}
-
 // the kernel that runs pass i: the wave-split kernel where every round trip splits at a wave position
 // and the block shape has one, the half-buffer kernel where every round trip splits, else the full one
 static int pass_variant(const StagedPlan *p, size_t i)
@@ -1335,55 +1211,25 @@ static int pass_variant(const StagedPlan *p, size_t i)
 
 static int launch_pass(StagedPlan *p, qsim_state *s, size_t i, int init_zero, const double *scale, double *norm)
 {
-    const int v = p->log_e * 16 + p->log_t;
-    const int var = pass_variant(p, i);
-    if (var == QSIM_STAGED_WAVE && p->dtype == QSIM_C128) {
-        if (v == 4 * 16 + 7) launch_wave<double, 4, 7, 4>(p, s, i, init_zero, scale, norm);
-        else launch_wave<double, 4, 8, 4>(p, s, i, init_zero, scale, norm);
-        QSIM_HIP(hipGetLastError());
-        return QSIM_OK;
-    }
-    if (var == QSIM_STAGED_WAVE) {
-        if (v == 5 * 16 + 7) launch_wave<float, 5, 7, 4>(p, s, i, init_zero, scale, norm);
-        else launch_wave<float, 5, 8, 4>(p, s, i, init_zero, scale, norm);
-        QSIM_HIP(hipGetLastError());
-        return QSIM_OK;
-    }
-    if (var == QSIM_STAGED_HALF) {
-        switch ((p->dtype == QSIM_C128 ? 256 : 0) + v) {
-        case 256 + 4 * 16 + 6: launch_half<double, 4, 6, 3>(p, s, i, init_zero, scale, norm); break;
-        case 256 + 4 * 16 + 7: launch_half<double, 4, 7, 3>(p, s, i, init_zero, scale, norm); break;
-        case 256 + 4 * 16 + 8: launch_half<double, 4, 8, 3>(p, s, i, init_zero, scale, norm); break;
-        case 5 * 16 + 6: launch_half<float, 5, 6, 3>(p, s, i, init_zero, scale, norm); break;
-        case 5 * 16 + 7: launch_half<float, 5, 7, 3>(p, s, i, init_zero, scale, norm); break;
-        case 5 * 16 + 8: launch_half<float, 5, 8, 3>(p, s, i, init_zero, scale, norm); break;
-        default: return set_error(QSIM_EINVAL, "staged: no half-buffer kernel for this block shape");
-        }
-        QSIM_HIP(hipGetLastError());
-        return QSIM_OK;
-    }
-    if (p->dtype == QSIM_C128) {
-        switch (v) {
-        case 3 * 16 + 7: launch_variant<double, 3, 7, 4>(p, s, i, init_zero, scale, norm); break;
-        case 3 * 16 + 8: launch_variant<double, 3, 8, 4>(p, s, i, init_zero, scale, norm); break;
-        case 3 * 16 + 9: launch_variant<double, 3, 9, 3>(p, s, i, init_zero, scale, norm); break;
-        case 4 * 16 + 6: launch_variant<double, 4, 6, 2>(p, s, i, init_zero, scale, norm); break;
-        case 4 * 16 + 7: launch_variant<double, 4, 7, 2>(p, s, i, init_zero, scale, norm); break;
-        case 4 * 16 + 9: launch_variant<double, 4, 9, 2>(p, s, i, init_zero, scale, norm); break;  // 13 resident qubits, one workgroup per CU
-        default: launch_variant<double, 4, 8, 2>(p, s, i, init_zero, scale, norm); break;
-        }
-    } else {
-        switch (v) {
-        case 4 * 16 + 7: launch_variant<float, 4, 7, 3>(p, s, i, init_zero, scale, norm); break;
-        case 4 * 16 + 8: launch_variant<float, 4, 8, 3>(p, s, i, init_zero, scale, norm); break;
-        case 4 * 16 + 9: launch_variant<float, 4, 9, 2>(p, s, i, init_zero, scale, norm); break;
-        case 5 * 16 + 6: launch_variant<float, 5, 6, 1>(p, s, i, init_zero, scale, norm); break;
-        case 5 * 16 + 7: launch_variant<float, 5, 7, 1>(p, s, i, init_zero, scale, norm); break;
-        case 5 * 16 + 9: launch_variant<float, 5, 9, 1>(p, s, i, init_zero, scale, norm); break;   // 14 resident qubits, one workgroup per CU
-        case 4 * 16 + 10: launch_variant<float, 4, 10, 4>(p, s, i, init_zero, scale, norm); break; // 14 resident qubits, 1024 threads
-        default: launch_variant<float, 5, 8, 1>(p, s, i, init_zero, scale, norm); break;
-        }
-    }
+    PassLaunch a{};
+    a.data = s->data;
+    a.pass = p->d_passes + i;
+    a.stages = p->d_stages;
+    a.rounds = p->d_rounds;
+    a.ops = p->d_ops;
+    a.blks = p->d_blks;
+    a.scale = scale;
+    a.norm = norm;
+    a.grid = unsigned(dim(p->n - p->m));
+    a.stream = s->stream;
+    a.mode = init_zero ? 2 : (scale || norm) ? 1 : 0;
+    const int form = pass_variant(p, i);
+    int rc;
+    if (p->dtype == QSIM_C128)
+        rc = form == QSIM_STAGED_WAVE ? launch_wave_c128(p->log_e, p->log_t, a) : launch_pass_c128(form, p->log_e, p->log_t, a);
+    else
+        rc = form == QSIM_STAGED_WAVE ? launch_wave_c64(p->log_e, p->log_t, a) : launch_pass_c64(form, p->log_e, p->log_t, a);
+    if (rc) return rc;
     QSIM_HIP(hipGetLastError());
     return QSIM_OK;
 }

@@ -1115,6 +1115,29 @@ __device__ __forceinline__ void run_block_wave(T *__restrict__ a, const SPass &p
     if (EDGE && edge.norm) edge_norm_out(nacc, edge.norm, blk, lds);
 }
 
+// One launch of a staged pass: its tables, the optional renormalisation edge (see SEdge) and the kernel
+// mode (0: reads the state; 1: folds a renormalisation point; 2: first pass of a run from |0...0>).
+struct PassLaunch {
+    void *data;
+    const SPass *pass;
+    const SStage *stages;
+    const SRound *rounds;
+    const SOp *ops;
+    const SBlk *blks;
+    const double *scale;
+    double *norm;
+    unsigned grid;
+    hipStream_t stream;
+    int mode;
+};
+// launch the pass kernel of a block shape (2^log_e amplitudes per thread, 2^log_t threads) in the
+// given form (QSIM_STAGED_FULL or QSIM_STAGED_HALF; the wave form through launch_wave_*); EINVAL if the
+// shape has no such kernel
+int launch_pass_c128(int form, int log_e, int log_t, const PassLaunch &a);
+int launch_pass_c64(int form, int log_e, int log_t, const PassLaunch &a);
+int launch_wave_c128(int log_e, int log_t, const PassLaunch &a);
+int launch_wave_c64(int log_e, int log_t, const PassLaunch &a);
+
 // host: append the schedule of one circuit (see staged.hip)
 int staged_schedule(int n, int dtype, int m, int log_e, const std::vector<qsim_gate> &gates, std::vector<SPass> &passes,
                     std::vector<SStage> &stages, std::vector<SRound> &rounds, std::vector<SOp> &ops,
