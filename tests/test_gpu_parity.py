@@ -438,6 +438,28 @@ def test_plan_renormalisation_points(q, oracle_mod, dtype, method, m, le):
             s2.close()
 
 
+@pytest.mark.parametrize("dtype,method", [("c128", "plain"), ("c128", "staged"), ("c64", "staged")])
+def test_renorm_only_plan(q, oracle_mod, dtype, method):
+    """A plan of two renormalisation points and no gate: its norms read 0 before the first execution;
+    on an unnormalised state it runs a norm sweep and a scaling sweep per point and leaves the
+    normalised state; the points report the state's squared norm, then 1."""
+    n = 13
+    text = wl.circuit_text(n, ["RENORM", "RENORM"])
+    psi0 = 3.0 * wl.gaussian_state(n, 4)
+    ref = oracle_mod.run_circuit(text, psi0=psi0)
+    p = q.Plan(q.parse_circuit(text), dtype, method=method)
+    assert np.array_equal(p.norms(), np.zeros(2))
+    s = gpu_state(q, psi0, dtype)
+    p.execute(s)
+    compare_circuit(s.download().astype(np.complex128), ref, dtype, f"{method} renorm only")
+    rtol = 1e-12 if dtype == "c128" else 1e-5
+    np.testing.assert_allclose(p.norms(), [oracle_mod.norm(psi0), 1.0], rtol=rtol)
+    p.execute_from_zero(s)  # |0...0> first, then the points
+    np.testing.assert_allclose(p.norms(), [1.0, 1.0], rtol=rtol)
+    p.close()
+    s.close()
+
+
 def test_renorm_point_rejected_outside_plans(q):
     c = q.parse_circuit(wl.circuit_text(4, ["H 0", "RENORM"]))
     with pytest.raises(q.QsimError):
