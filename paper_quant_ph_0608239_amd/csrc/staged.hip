@@ -17,6 +17,7 @@
 // usual RB/TB splits are free of bank conflicts.
 #include <algorithm>
 #include <functional>
+#include <map>
 #include <utility>
 #include <array>
 #include <cstring>
@@ -824,7 +825,7 @@ static bool assign_half(SPass &ps, std::vector<SStage> &stages, int m, int log_e
 
 int staged::staged_schedule(int n, int dtype, int m, int log_e, const std::vector<qsim_gate> &gates,
                             std::vector<SPass> &passes, std::vector<SStage> &stages, std::vector<SRound> &rounds,
-                            std::vector<SOp> &ops, std::vector<SBlk> &blks)
+                            std::vector<SOp> &ops, std::vector<SBlk> &blks, int search_width)
 {
     if (m > kMaxM || log_e < 1 || log_e > kMaxLogE || m - log_e > kMaxLogT || m - log_e < 0)
         return set_error(QSIM_EINVAL, "staged: block shape outside the kernel tables");
@@ -836,14 +837,14 @@ int staged::staged_schedule(int n, int dtype, int m, int log_e, const std::vecto
     std::vector<char> done(G, 0);
     size_t ndone = 0;
 
-    // gates that a pass with resident set R executes, in circuit order: a gate runs when none of its
-    // qubits is held back by an earlier gate that does not run, and it is diagonal or its target(s)
-    // are resident
-    auto executable = [&](uint64_t R, std::vector<size_t> *take) {
+    // gates that a pass with resident set R executes after the gates marked in dn, in circuit order:
+    // a gate runs when none of its qubits is held back by an earlier gate that does not run, and it is
+    // diagonal or its target(s) are resident
+    auto executable = [&](const std::vector<char> &dn, uint64_t R, std::vector<size_t> *take) {
         int dense = 0, all = 0;
         uint64_t blocked = 0;
         for (size_t i = 0; i < G; ++i) {
-            if (done[i]) continue;
+            if (dn[i]) continue;
             const GInfo &g = gi[i];
             if (g.qmask & blocked) {
                 blocked |= g.qmask;
@@ -861,15 +862,15 @@ int staged::staged_schedule(int n, int dtype, int m, int log_e, const std::vecto
         }
         return std::make_pair(dense, all);
     };
-    while (ndone < G) {
-        // --- resident set. Candidates: the low run plus the targets of the earliest pending
-        // non-diagonal gates, and the low run plus every window of m - L consecutive qubits above it
-        // (a window lets a pass run the light cone of neighbouring-qubit circuits several layers
-        // deep). The pass takes the candidate that executes the most non-diagonal gates.
+    // Resident-set candidates of the next pass: the low run plus the targets of the earliest pending
+    // non-diagonal gates, and the low run plus every window of m - L consecutive qubits above it (a
+    // window lets a pass run the light cone of neighbouring-qubit circuits several layers deep).
+    auto candidates = [&](const std::vector<char> &dn) {
+        std::vector<uint64_t> c;
         uint64_t R = (uint64_t(1) << L) - 1;
         int cnt = L;
         for (size_t i = 0; i < G && cnt < m; ++i) {
-            if (done[i] || diagonal(gi[i])) continue;
+            if (dn[i] || diagonal(gi[i])) continue;
             const int tg[2] = {gi[i].target, gi[i].target2};
             const int need = (gi[i].kind == G_SWAP) ? 2 : 1;
             int missing = 0;
@@ -887,18 +888,90 @@ int staged::staged_schedule(int n, int dtype, int m, int log_e, const std::vecto
                 R |= uint64_t(1) << q;
                 ++cnt;
             }
-        {
-            std::pair<int, int> best = executable(R, nullptr);
-            const int w = m - L;
-            for (int a = L; a + w <= n; ++a) {
-                const uint64_t Rw = ((uint64_t(1) << L) - 1) | (((uint64_t(1) << w) - 1) << a);
-                const std::pair<int, int> c = executable(Rw, nullptr);
-                if (c.first > best.first || (c.first == best.first && c.second > best.second)) {
-                    best = c;
-                    R = Rw;
-                }
+        c.push_back(R);
+        const int w = m - L;
+        for (int a = L; a + w <= n; ++a) {
+            const uint64_t Rw = ((uint64_t(1) << L) - 1) | (((uint64_t(1) << w) - 1) << a);
+            if (Rw != R) c.push_back(Rw);
+        }
+        return c;
+    };
+    // the greedy rule: the candidate that executes the most non-diagonal gates (then the most gates)
+    auto greedy = [&](const std::vector<char> &dn) {
+        const std::vector<uint64_t> c = candidates(dn);
+        uint64_t R = c[0];
+        std::pair<int, int> best = executable(dn, R, nullptr);
+        for (size_t k = 1; k < c.size(); ++k) {
+            const std::pair<int, int> e = executable(dn, c[k], nullptr);
+            if (e > best) {
+                best = e;
+                R = c[k];
             }
         }
+        return R;
+    };
+    // Passes are costed mostly per pass (each moves the whole state through HBM once), so the schedule
+    // wants few of them. The greedy rule fills each pass, but a pass that leaves the frontier of
+    // neighbouring-qubit circuits ragged costs later passes. A beam search over the candidate sequences
+    // (states ranked by the non-diagonal gates run so far, the best `width` kept per depth, equal gate
+    // sets merged) replaces the greedy sequence where it finishes in fewer passes. Its work is bounded
+    // by a budget of gate visits; a circuit too large for it keeps the greedy sequence.
+    std::vector<uint64_t> chosen;  // resident set of each pass, empty: decide greedily pass by pass
+    if (search_width > 1 && G > 0) {
+        std::vector<char> dn(G, 0);
+        std::vector<uint64_t> gseq;
+        size_t left = G;
+        while (left > 0) {
+            const uint64_t R = greedy(dn);
+            std::vector<size_t> take;
+            executable(dn, R, &take);
+            if (take.empty()) break;
+            for (size_t i : take) dn[i] = 1;
+            left -= take.size();
+            gseq.push_back(R);
+        }
+        const double ncand = double(std::max(1, n - (m - L) - L + 2));
+        const double per_width = double(gseq.size()) * ncand * double(G);
+        const int width = int(std::min<double>(search_width, 4.0e8 / std::max(1.0, per_width)));
+        if (left == 0 && gseq.size() > 1 && width > 1) {
+            struct St {
+                std::vector<char> dn;
+                int dense, all;
+                std::vector<uint64_t> seq;
+            };
+            std::vector<St> level(1, St{std::vector<char>(G, 0), 0, 0, {}});
+            std::vector<uint64_t> found;
+            for (size_t depth = 1; depth < gseq.size() && found.empty(); ++depth) {
+                std::map<std::vector<char>, size_t> seen;
+                std::vector<St> next;
+                for (const St &s : level) {
+                    for (uint64_t R : candidates(s.dn)) {
+                        std::vector<size_t> take;
+                        const std::pair<int, int> e = executable(s.dn, R, &take);
+                        if (take.empty()) continue;
+                        St t{s.dn, s.dense + e.first, s.all + e.second, s.seq};
+                        for (size_t i : take) t.dn[i] = 1;
+                        t.seq.push_back(R);
+                        auto it = seen.find(t.dn);
+                        if (it != seen.end()) continue;  // the same gates done: the first sequence stays
+                        seen.emplace(t.dn, next.size());
+                        if (size_t(t.all) == G && found.empty()) found = t.seq;
+                        next.push_back(std::move(t));
+                    }
+                }
+                std::stable_sort(next.begin(), next.end(), [](const St &a, const St &b) {
+                    return a.dense != b.dense ? a.dense > b.dense : a.all > b.all;
+                });
+                if (next.size() > size_t(width)) next.resize(size_t(width));
+                level.swap(next);
+            }
+            if (!found.empty() && found.size() < gseq.size()) chosen = found;
+        }
+    }
+    size_t npass = 0;
+    while (ndone < G) {
+        uint64_t R = npass < chosen.size() ? chosen[npass] : greedy(done);
+        ++npass;
         SPass ps{};
         ps.m = m;
         int localof[64];
@@ -917,7 +990,7 @@ int staged::staged_schedule(int n, int dtype, int m, int log_e, const std::vecto
         };
         // --- executable gates, in circuit order
         std::vector<size_t> take;
-        executable(R, &take);
+        executable(done, R, &take);
         // --- stages: a stage holds dense ops on at most log_e distinct resident targets (its
         // register bits) and diagonal ops on any qubits; a quantum swap ends it
         ps.stage_begin = int(stages.size());
@@ -1095,7 +1168,7 @@ int staged_build(int n, int dtype, const std::vector<qsim_gate> &gates, int lds_
     for (size_t k = 0; k < segs.size(); ++k) {
         seg_first[k] = int(passes.size());
         if (!segs[k].empty())
-            if (int rc = staged_schedule(n, dtype, m, log_e, segs[k], passes, stages, rounds, ops, blks)) return rc;
+            if (int rc = staged_schedule(n, dtype, m, log_e, segs[k], passes, stages, rounds, ops, blks, kPassSearchWidth)) return rc;
         seg_end[k] = int(passes.size());
     }
     StagedPlan *p = new StagedPlan();

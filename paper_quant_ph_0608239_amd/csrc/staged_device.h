@@ -1138,10 +1138,13 @@ int launch_pass_c64(int form, int log_e, int log_t, const PassLaunch &a);
 int launch_wave_c128(int log_e, int log_t, const PassLaunch &a);
 int launch_wave_c64(int log_e, int log_t, const PassLaunch &a);
 
-// host: append the schedule of one circuit (see staged.hip)
+// host: append the schedule of one circuit (see staged.hip). search_width > 1: resident sets from a
+// bounded beam search of that width where it needs fewer passes than the greedy rule (plans use
+// kPassSearchWidth)
+constexpr int kPassSearchWidth = 32;
 int staged_schedule(int n, int dtype, int m, int log_e, const std::vector<qsim_gate> &gates, std::vector<SPass> &passes,
                     std::vector<SStage> &stages, std::vector<SRound> &rounds, std::vector<SOp> &ops,
-                    std::vector<SBlk> &blks);
+                    std::vector<SBlk> &blks, int search_width = 1);
 bool staged_variant_ok(int dtype, int log_e, int log_t);
 __global__ void k_op_angles(SOp *ops, int nops);
 

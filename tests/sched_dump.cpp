@@ -1,6 +1,7 @@
 // Test helper (host only): run the staged scheduler of libqsim on a gate list and write its tables, so
 // that a CPU test can check them. Usage: sched_dump <gates.bin> <n> <dtype> <m> <log_e> <out.bin>.
-// gates.bin holds qsim_gate records; out.bin holds the five record sizes, the five table lengths and
+// An optional seventh argument sets the width of the pass search (default: the one plans use; 1: the
+// greedy rule alone). gates.bin holds qsim_gate records; out.bin holds the five record sizes, the five table lengths and
 // the pass, stage, round, op and two-qubit block tables.
 #include <cstdint>
 #include <cstdio>
@@ -13,8 +14,8 @@ using namespace qsim::staged;
 
 int main(int argc, char **argv)
 {
-    if (argc != 7) {
-        std::fprintf(stderr, "usage: sched_dump gates.bin n dtype m log_e out.bin\n");
+    if (argc != 7 && argc != 8) {
+        std::fprintf(stderr, "usage: sched_dump gates.bin n dtype m log_e out.bin [search_width]\n");
         return 2;
     }
     std::FILE *f = std::fopen(argv[1], "rb");
@@ -29,7 +30,8 @@ int main(int argc, char **argv)
     std::vector<SOp> ops;
     std::vector<SBlk> blks;
     const int rc = staged_schedule(std::atoi(argv[2]), std::atoi(argv[3]), std::atoi(argv[4]), std::atoi(argv[5]), gates,
-                                   passes, stages, rounds, ops, blks);
+                                   passes, stages, rounds, ops, blks,
+                                   argc == 8 ? std::atoi(argv[7]) : kPassSearchWidth);
     if (rc) {
         std::printf("rc=%d\n", rc);
         return 1;
