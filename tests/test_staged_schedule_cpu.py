@@ -32,11 +32,13 @@ def dumper(tmp_path_factory):
     return out
 
 
-def tables(dumper, tmp_path, text, n, c128, m, le):
+def tables(dumper, tmp_path, text, n, c128, m, le, width=None):
+    """Tables of the plan scheduler (width None: the pass search plans use; 1: the greedy rule)."""
     gates = tmp_path / "g.bin"
     gates.write_bytes(bytes(parse_circuit(text).gate_array()))
     out = tmp_path / "s.bin"
-    r = subprocess.run([dumper, str(gates), str(n), "1" if c128 else "0", str(m), str(le), str(out)],
+    extra = [] if width is None else [str(width)]
+    r = subprocess.run([dumper, str(gates), str(n), "1" if c128 else "0", str(m), str(le), str(out)] + extra,
                        capture_output=True, text=True)
     assert r.returncode == 0, r.stdout + r.stderr
     return sm.load_tables(str(out))
@@ -96,6 +98,22 @@ def test_schedule_reproduces_oracle(dumper, tmp_path, oracle_mod, case, c128, m,
     sm.check_half_exchanges(P, S, m, le, c128)
     if m - le >= 7:
         sm.check_wave_barriers(P, S, m, le)
+
+
+@pytest.mark.parametrize("n,layers,m", [(16, 10, 10), (17, 8, 10)])
+def test_pass_search_saves_passes_and_reproduces_oracle(dumper, tmp_path, oracle_mod, n, layers, m):
+    """On brickworks where the greedy choice of resident sets leaves a ragged frontier, the plans' pass
+    search finds a sequence with one pass fewer; that schedule still reproduces the oracle and keeps
+    its LDS exchanges and barriers valid."""
+    text = wl.brickwork_circuit(n, layers, seed=21)
+    greedy = tables(dumper, tmp_path, text, n, True, m, 4, width=1)
+    P, S, RD, O, B = tables(dumper, tmp_path, text, n, True, m, 4)
+    assert len(P) == len(greedy[0]) - 1
+    psi0 = wl.gaussian_state(n, 3)
+    ref = oracle_mod.run_circuit(text, psi0=psi0)
+    got = sm.run_schedule(psi0, n, m, 4, P, S, RD, O, B)
+    assert np.max(np.abs(got - ref)) < 1e-12
+    sm.check_half_exchanges(P, S, m, 4, True)
 
 
 def test_brickwork_passes_use_wave_splits(dumper, tmp_path):
