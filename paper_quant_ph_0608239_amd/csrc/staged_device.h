@@ -296,24 +296,54 @@ __device__ __forceinline__ void op_dense_flip_pair(typename Vec<T>::C *x, const 
 // A dense op with a fused flip chosen per lane (a thread bit): every pair of the lanes that take it
 // uses the 2x2 with row 1 (or column 1) negated. (A sign xor of the data instead needs the flip on
 // one side of the 2x2 or the other; a branch on that side made the compiler copy the amplitudes.)
+// the coefficient with its sign bit xor-ed with t (0 or the sign bit): an exact negation where t is set
+__device__ __forceinline__ double xsign(double c, uint32_t t)
+{
+    uint2 w = __builtin_bit_cast(uint2, c);
+    w.y ^= t;
+    return __builtin_bit_cast(double, w);
+}
+__device__ __forceinline__ float xsign(float c, uint32_t t) { return __builtin_bit_cast(float, __builtin_bit_cast(uint32_t, c) ^ t); }
+
+// c where keep is all ones, 0 where it is 0 (bitwise: exact)
+__device__ __forceinline__ double bmask(double c, uint32_t keep)
+{
+    uint2 w = __builtin_bit_cast(uint2, c);
+    w.x &= keep;
+    w.y &= keep;
+    return __builtin_bit_cast(double, w);
+}
+__device__ __forceinline__ float bmask(float c, uint32_t keep) { return __builtin_bit_cast(float, __builtin_bit_cast(uint32_t, c) & keep); }
+// c where keep is all ones, 1 where it is 0 (bitwise: exact)
+__device__ __forceinline__ double bsel_one(double c, uint32_t keep)
+{
+    uint2 w = __builtin_bit_cast(uint2, c);
+    w.x &= keep;
+    w.y = (w.y & keep) | (0x3ff00000u & ~keep);
+    return __builtin_bit_cast(double, w);
+}
+__device__ __forceinline__ float bsel_one(float c, uint32_t keep)
+{
+    return __builtin_bit_cast(float, (__builtin_bit_cast(uint32_t, c) & keep) | (0x3f800000u & ~keep));
+}
+
 template <typename T, int E, int RB>
 __device__ __forceinline__ void op_dense_alt_lane(typename Vec<T>::C *x, const SOp &op, uint32_t et, uint64_t base)
 {
     const T *c = coef<T>(op);
-    const bool neg = (base & op.galt) == op.galt && (et & op.alt_lcm) == op.alt_lcm;
+    // the lane's sign mask, applied to column 1 (column flip) or row 1 (row flip) and to u11
+    const uint32_t t = ((base & op.galt) == op.galt && (et & op.alt_lcm) == op.alt_lcm) ? 0x80000000u : 0u;
+    const uint32_t col = op.alt_col ? ~0u : 0u;
+    const uint32_t t1 = t & col, t2 = t & ~col;
     U2<T> w;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        w.r[k] = c[2 * k];
-        w.i[k] = c[2 * k + 1];
-    }
-    const bool n1 = neg && op.alt_col, n2 = neg && !op.alt_col;
-    w.r[1] = n1 ? -w.r[1] : w.r[1];
-    w.i[1] = n1 ? -w.i[1] : w.i[1];
-    w.r[2] = n2 ? -w.r[2] : w.r[2];
-    w.i[2] = n2 ? -w.i[2] : w.i[2];
-    w.r[3] = neg ? -w.r[3] : w.r[3];
-    w.i[3] = neg ? -w.i[3] : w.i[3];
+    w.r[0] = c[0];
+    w.i[0] = c[1];
+    w.r[1] = xsign(c[2], t1);
+    w.i[1] = xsign(c[3], t1);
+    w.r[2] = xsign(c[4], t2);
+    w.i[2] = xsign(c[5], t2);
+    w.r[3] = xsign(c[6], t);
+    w.i[3] = xsign(c[7], t);
 #pragma unroll
     for (int r = 0; r < E; ++r)
         if (!((r >> RB) & 1)) pair2x2_rc<T, false>(x[r], x[r | (1 << RB)], w);
@@ -325,12 +355,15 @@ template <typename T, int E, int RB>
 __device__ __forceinline__ void op_dense_cond(typename Vec<T>::C *x, const SOp &op, bool lane_ok)
 {
     const T *c = coef<T>(op);
+    // lanes that fail the condition take the identity: the coefficients' bits are masked (off-diagonal
+    // and imaginary parts to 0) and the diagonal's real parts bit-selected against 1
+    const uint32_t keep = lane_ok ? ~0u : 0u;
     U2<T> u;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         const bool dg = (k == 0 || k == 3);
-        u.r[k] = lane_ok ? c[2 * k] : (dg ? T(1) : T(0));
-        u.i[k] = lane_ok ? c[2 * k + 1] : T(0);
+        u.r[k] = dg ? bsel_one(c[2 * k], keep) : bmask(c[2 * k], keep);
+        u.i[k] = bmask(c[2 * k + 1], keep);
     }
 #pragma unroll
     for (int r = 0; r < E; ++r) {
