@@ -17,7 +17,7 @@
 // usual RB/TB splits are free of bank conflicts.
 #include <algorithm>
 #include <functional>
-#include <map>
+#include <set>
 #include <utility>
 #include <array>
 #include <cstring>
@@ -942,7 +942,7 @@ int staged::staged_schedule(int n, int dtype, int m, int log_e, const std::vecto
             std::vector<St> level(1, St{std::vector<char>(G, 0), 0, 0, {}});
             std::vector<uint64_t> found;
             for (size_t depth = 1; depth < gseq.size() && found.empty(); ++depth) {
-                std::map<std::vector<char>, size_t> seen;
+                std::set<std::vector<char>> seen;
                 std::vector<St> next;
                 for (const St &s : level) {
                     for (uint64_t R : candidates(s.dn)) {
@@ -952,9 +952,7 @@ int staged::staged_schedule(int n, int dtype, int m, int log_e, const std::vecto
                         St t{s.dn, s.dense + e.first, s.all + e.second, s.seq};
                         for (size_t i : take) t.dn[i] = 1;
                         t.seq.push_back(R);
-                        auto it = seen.find(t.dn);
-                        if (it != seen.end()) continue;  // the same gates done: the first sequence stays
-                        seen.emplace(t.dn, next.size());
+                        if (!seen.insert(t.dn).second) continue;  // the same gates done: the first sequence stays
                         if (size_t(t.all) == G && found.empty()) found = t.seq;
                         next.push_back(std::move(t));
                     }
