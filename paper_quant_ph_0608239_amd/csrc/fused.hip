@@ -1,14 +1,16 @@
 // Dense k-qubit gates (1 <= k <= 5): for every base index b with zero bits at the gate qubits,
 // v_r = a(b + off[r]) (off[r] = sum_s bit_s(r) 2^qubits[s]) is replaced by U v.
 //
-// k >= 4: a true dense contraction Y = W X on the matrix cores. With K = 2^k amplitudes per column,
-// X is 2K x 2^(n-k) real (rows 0..K-1 = real parts, K..2K-1 = imaginary parts of the K amplitudes
-// of a column) and W = [[Ur, -Ui], [Ui, Ur]] is 2K x 2K. One wave computes 16 columns at a time with
-// v_mfma_f64_16x16x4f64 (complex128) or v_mfma_f32_16x16x4f32 (complex64, FP32 accumulation):
-// lane l owns column l % 16 and K-row group l / 16. With the real/imaginary split of the rows,
-// a lane loads whole amplitudes (16 B / 8 B) for K-step kk and kk + KS/2, and stores whole
-// amplitudes from the accumulators of row blocks mb and mb + MB/2. W is staged in LDS in fragment
-// order, so every A-operand read is one conflict-free ds_read per lane.
+// k >= 4: a dense contraction on the matrix cores. With K = 2^k amplitudes per column, X = Xr + i Xi
+// (K x 2^(n-k), split into real and imaginary parts) goes to Y = U X through three real K x K products
+// (the three-multiplication form of a complex product): T1 = Ur Xr, T2 = Ui Xi, T3 = (Ur + Ui)(Xr + Xi),
+// then Yr = T1 - T2 and Yi = T3 - T1 - T2. That is 3 K^2 multiply-adds per column on the matrix cores
+// instead of the 4 K^2 of the real form [[Ur, -Ui], [Ui, Ur]], for 2 K additions per column on the
+// vector ALU. One wave computes 16 columns at a time with v_mfma_f64_16x16x4f64 (complex128) or
+// v_mfma_f32_16x16x4f32 (complex64, FP32 accumulation): lane l owns column l % 16 and K-row group
+// l / 16. A lane loads whole amplitudes (16 B / 8 B), one per K-step, and stores whole amplitudes from
+// the accumulators of the same row positions. The three matrices are staged in LDS in fragment order,
+// so every A-operand read is one conflict-free ds_read per lane.
 //
 // k <= 3: one lane per column on the vector ALUs, U in kernel arguments.
 #include "qsim_internal.h"
@@ -64,9 +66,8 @@ template <typename T> __host__ __device__ inline int amp_of(int kk, int kq);
 template <> __host__ __device__ inline int amp_of<double>(int kk, int kq) { return 4 * kk + kq; }
 template <> __host__ __device__ inline int amp_of<float>(int kk, int kq) { return 16 * (kk >> 2) + 4 * kq + (kk & 3); }
 
-// Fragment order of W: frag[(mb * KS + kk) * 64 + l] = W[16 mb + l % 16][col(kk, l / 16)] where the
-// K index of step kk for lane group kq is the real part of amp_of(kk, kq) (kk < KS/2) or the
-// imaginary part of amp_of(kk - KS/2, kq).
+// Fragment order of the three matrices M_0 = Ur, M_1 = Ui, M_2 = Ur + Ui:
+// frag[((p * MB + mb) * KS + kk) * 64 + l] = M_p[16 mb + l % 16][amp_of(kk, l / 16)].
 template <typename T, int KLOG>
 __global__ __launch_bounds__(kBlock) void k_fused_mfma(T *__restrict__ a, uint64_t ntiles, IndexMap map, QubitList ql,
                                                       const T *__restrict__ wfrag)
@@ -74,21 +75,22 @@ __global__ __launch_bounds__(kBlock) void k_fused_mfma(T *__restrict__ a, uint64
     using C = typename Vec<T>::C;
     using AV = typename Acc<T>::V;
     constexpr int K = 1 << KLOG;   // amplitudes per column
-    constexpr int R2 = 2 * K;      // real rows
-    constexpr int KS = R2 / 4;     // K-steps of 4
-    constexpr int MB = R2 / 16;    // output row blocks of 16
-    constexpr int NA = KS / 2;     // amplitudes per lane per column tile
-    __shared__ T W[R2 * R2];
-    for (int i = threadIdx.x; i < R2 * R2; i += kBlock) W[i] = wfrag[i];
+    constexpr int KS = K / 4;      // K-steps of 4 (one amplitude per lane each)
+    constexpr int MB = K / 16;     // output row blocks of 16
+    constexpr int NA = KS;         // amplitudes per lane per column tile
+    constexpr int FR = MB * KS * 64;  // fragment words of one matrix
+    __shared__ T W[3 * FR];
+    for (int i = threadIdx.x; i < 3 * FR; i += kBlock) W[i] = wfrag[i];
     __syncthreads();
 
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int col = lane & 15;
     const int kq = lane >> 4;
-    uint64_t off[NA];
-#pragma unroll
-    for (int kk = 0; kk < NA; ++kk) off[kk] = offset_of(amp_of<T>(kk, kq), ql);
+    // offset of the amplitude a lane loads at K-step kk: the lane-group part (bits of kq) plus a
+    // wave-uniform part (bits of kk), which occupy disjoint bits of amp_of
+    const uint64_t dq = offset_of(amp_of<T>(0, kq), ql);
+    auto off = [&](int kk) { return dq + offset_of(amp_of<T>(kk, 0), ql); };
 
     const uint64_t wstride = uint64_t(gridDim.x) * (kBlock / 64);
     uint64_t tile = uint64_t(blockIdx.x) * (kBlock / 64) + wave;
@@ -96,11 +98,11 @@ __global__ __launch_bounds__(kBlock) void k_fused_mfma(T *__restrict__ a, uint64
     if (tile < ntiles) {
         const uint64_t b = insert_zeros(tile * 16 + col, map);
 #pragma unroll
-        for (int kk = 0; kk < NA; ++kk) x[kk] = *reinterpret_cast<const C *>(a + 2 * (b + off[kk]));
+        for (int kk = 0; kk < NA; ++kk) x[kk] = *reinterpret_cast<const C *>(a + 2 * (b + off(kk)));
     }
     while (tile < ntiles) {
-        // W stays in LDS and is re-read every tile (a compiler barrier keeps it from being hoisted
-        // into 2^(2k-4) registers per lane), which leaves room for more resident waves
+        // the matrices stay in LDS and are re-read every tile (a compiler barrier keeps them from being
+        // hoisted into registers), which leaves room for more resident waves
         asm volatile("" ::: "memory");
         const uint64_t b = insert_zeros(tile * 16 + col, map);
         const uint64_t next = tile + wstride;
@@ -109,24 +111,36 @@ __global__ __launch_bounds__(kBlock) void k_fused_mfma(T *__restrict__ a, uint64
         if (next < ntiles) {
             const uint64_t bn = insert_zeros(next * 16 + col, map);
 #pragma unroll
-            for (int kk = 0; kk < NA; ++kk) xn[kk] = *reinterpret_cast<const C *>(a + 2 * (bn + off[kk]));
+            for (int kk = 0; kk < NA; ++kk) xn[kk] = *reinterpret_cast<const C *>(a + 2 * (bn + off(kk)));
         }
-        // K-step outer, row block inner: the MB accumulator chains are independent, so
+        // K-step outer, product and row block inner: the 3 MB accumulator chains are independent, so
         // consecutive matrix-core instructions never wait on each other's results
-        AV acc[MB];
+        AV t1[MB], t2[MB], t3[MB];
 #pragma unroll
-        for (int mb = 0; mb < MB; ++mb) acc[mb] = AV{0, 0, 0, 0};
+        for (int mb = 0; mb < MB; ++mb) {
+            t1[mb] = AV{0, 0, 0, 0};
+            t2[mb] = AV{0, 0, 0, 0};
+            t3[mb] = AV{0, 0, 0, 0};
+        }
 #pragma unroll
         for (int kk = 0; kk < KS; ++kk) {
-            const T bv = kk < NA ? x[kk].x : x[kk - NA].y;
+            const T xr = x[kk].x, xi = x[kk].y, xs = xr + xi;
 #pragma unroll
-            for (int mb = 0; mb < MB; ++mb) acc[mb] = mfma16(W[(mb * KS + kk) * 64 + lane], bv, acc[mb]);
+            for (int mb = 0; mb < MB; ++mb) {
+                const int f = (mb * KS + kk) * 64 + lane;
+                t1[mb] = mfma16(W[f], xr, t1[mb]);
+                t2[mb] = mfma16(W[FR + f], xi, t2[mb]);
+                t3[mb] = mfma16(W[2 * FR + f], xs, t3[mb]);
+            }
         }
 #pragma unroll
-        for (int mb = 0; mb < MB / 2; ++mb)
+        for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
-            for (int v = 0; v < 4; ++v)
-                *reinterpret_cast<C *>(a + 2 * (b + off[4 * mb + v])) = C{acc[mb][v], acc[mb + MB / 2][v]};
+            for (int v = 0; v < 4; ++v) {
+                const T yr = t1[mb][v] - t2[mb][v];
+                const T yi = t3[mb][v] - t1[mb][v] - t2[mb][v];
+                *reinterpret_cast<C *>(a + 2 * (b + off(4 * mb + v))) = C{yr, yi};
+            }
 #pragma unroll
         for (int kk = 0; kk < NA; ++kk) x[kk] = xn[kk];
         tile = next;
@@ -217,30 +231,26 @@ int fused_valu_t(qsim_state *s, int k, const QubitList &ql, const IndexMap &map,
 
 }  // namespace
 
-// W in fragment order for the MFMA kernel, in the state's precision
+// the three matrices of the MFMA kernel (Ur, Ui, Ur + Ui, sums formed in FP64) in fragment order, in
+// the state's precision
 template <typename T>
 static void build_wfrag(int k, const double *U, std::vector<T> &frag)
 {
-    const int K = 1 << k, R2 = 2 * K, KS = R2 / 4, MB = R2 / 16, NA = KS / 2;
-    auto Wreal = [&](int r, int c) -> double {
-        // W = [[Ur, -Ui], [Ui, Ur]]: rows/cols < K are real parts, >= K imaginary parts
-        const int ar = r % K, ac = c % K;
-        const double ur = U[2 * (ar * K + ac)], ui = U[2 * (ar * K + ac) + 1];
-        const bool rim = r >= K, cim = c >= K;
-        if (!rim && !cim) return ur;
-        if (!rim && cim) return -ui;
-        if (rim && !cim) return ui;
-        return ur;
+    const int K = 1 << k, KS = K / 4, MB = K / 16, FR = MB * KS * 64;
+    auto M = [&](int p, int r, int c) -> double {
+        const double ur = U[2 * (r * K + c)], ui = U[2 * (r * K + c) + 1];
+        return p == 0 ? ur : p == 1 ? ui : ur + ui;
     };
-    auto colidx = [&](int kk, int kq) { return kk < NA ? amp_of<T>(kk, kq) : K + amp_of<T>(kk - NA, kq); };
-    frag.assign(size_t(R2) * R2, T(0));
-    for (int mb = 0; mb < MB; ++mb)
-        for (int kk = 0; kk < KS; ++kk)
-            for (int l = 0; l < 64; ++l)
-                frag[size_t(mb * KS + kk) * 64 + l] = static_cast<T>(Wreal(16 * mb + l % 16, colidx(kk, l / 16)));
+    frag.assign(size_t(3) * FR, T(0));
+    for (int p = 0; p < 3; ++p)
+        for (int mb = 0; mb < MB; ++mb)
+            for (int kk = 0; kk < KS; ++kk)
+                for (int l = 0; l < 64; ++l)
+                    frag[size_t(p) * FR + size_t(mb * KS + kk) * 64 + l] =
+                        static_cast<T>(M(p, 16 * mb + l % 16, amp_of<T>(kk, l / 16)));
 }
 
-size_t wfrag_bytes(int k, int dtype) { return size_t(4) << (2 * k) << (dtype == QSIM_C128 ? 3 : 2); }
+size_t wfrag_bytes(int k, int dtype) { return size_t(3) << (2 * k) << (dtype == QSIM_C128 ? 3 : 2); }
 
 int build_wfrag_host(int k, int dtype, const double *U, void *host_out)
 {
