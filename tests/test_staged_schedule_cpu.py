@@ -100,20 +100,28 @@ def test_schedule_reproduces_oracle(dumper, tmp_path, oracle_mod, case, c128, m,
         sm.check_wave_barriers(P, S, m, le)
 
 
-@pytest.mark.parametrize("n,layers,m", [(16, 10, 10), (17, 8, 10)])
-def test_pass_search_saves_passes_and_reproduces_oracle(dumper, tmp_path, oracle_mod, n, layers, m):
-    """On brickworks where the greedy choice of resident sets leaves a ragged frontier, the plans' pass
-    search finds a sequence with one pass fewer; that schedule still reproduces the oracle and keeps
-    its LDS exchanges and barriers valid."""
-    text = wl.brickwork_circuit(n, layers, seed=21)
-    greedy = tables(dumper, tmp_path, text, n, True, m, 4, width=1)
-    P, S, RD, O, B = tables(dumper, tmp_path, text, n, True, m, 4)
+SEARCH_CASES = {
+    "brickwork16": lambda: (wl.brickwork_circuit(16, 10, seed=21), 16, True, 10, 4),
+    "brickwork17": lambda: (wl.brickwork_circuit(17, 8, seed=21), 17, True, 10, 4),
+    "qft15_with_swaps": lambda: (wl.qft_circuit(15), 15, True, 10, 4),
+    "mixed15_c64": lambda: (mixed_circuit(15, 150, 7), 15, False, 11, 5),
+}
+
+
+@pytest.mark.parametrize("case", sorted(SEARCH_CASES))
+def test_pass_search_saves_passes_and_reproduces_oracle(dumper, tmp_path, oracle_mod, case):
+    """Where the greedy choice of resident sets leaves a ragged frontier (brickworks, a QFT with its
+    swaps, random gates with controls and swaps), the plans' pass search finds a sequence with one pass
+    fewer; that schedule still reproduces the oracle and keeps its LDS exchanges valid."""
+    text, n, c128, m, le = SEARCH_CASES[case]()
+    greedy = tables(dumper, tmp_path, text, n, c128, m, le, width=1)
+    P, S, RD, O, B = tables(dumper, tmp_path, text, n, c128, m, le)
     assert len(P) == len(greedy[0]) - 1
     psi0 = wl.gaussian_state(n, 3)
     ref = oracle_mod.run_circuit(text, psi0=psi0)
-    got = sm.run_schedule(psi0, n, m, 4, P, S, RD, O, B)
+    got = sm.run_schedule(psi0, n, m, le, P, S, RD, O, B)
     assert np.max(np.abs(got - ref)) < 1e-12
-    sm.check_half_exchanges(P, S, m, 4, True)
+    sm.check_half_exchanges(P, S, m, le, c128)
 
 
 def test_brickwork_passes_use_wave_splits(dumper, tmp_path):
